@@ -1,0 +1,164 @@
+"""Benchmark: batched rank-Greville row updates on one MI355X.
+
+One step = reset every stream to the empty state, push all rows of the
+batched workload (B = 4096 independent streams, m ~ U{16..256},
+r ~ U{4..m/2}, n ~ U{m..8m}, FP32 state with FP64 rank decisions), and
+materialise every solution x_b.  Inputs are resident in HBM before the timed
+region.  The FP64 C oracle is then run on the same rows on the host cores
+(cpu_baseline) and every stream's x and rank are compared with it.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "row-updates/sec (batched FP32 vs plain FP64, 1 GPU) at stated error; % HBM/LDS BW"
+PEAK_HBM_GBS = 8000.0
+# FP32 (non-packed) and FP64 vector FMA: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+PEAK_ALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+
+def headroom(m, r):
+    """Rank capacity given to each stream: the planted rank plus 1/8 + 4."""
+    return np.minimum(m, r + (r + 7) // 8 + 4).astype(np.int32)
+
+
+def model(ms, rs, ns, s=4, s_in=4):
+    """Algorithmic flops and state bytes of one pass, from the rank
+    trajectory of these inputs: rows 0..r-1 are independent (rank i before
+    row i), the rest dependent at rank r.
+      dependent row:   flops 4 r m + 4 r^2,  bytes s (2 r m + 2 r^2) + s_in (m + 1)
+      independent row: flops 6 i m,          bytes s (4 i m + 2 m + 2 i + 1) + s_in (m + 1)
+    """
+    ms = ms.astype(np.float64)
+    rs = np.minimum(rs, ns).astype(np.float64)
+    ns = ns.astype(np.float64)
+    dep = ns - rs
+    sum_i = rs * (rs - 1) / 2.0
+    flops = dep * (4 * rs * ms + 4 * rs * rs) + 6 * sum_i * ms
+    byts = dep * (s * (2 * rs * ms + 2 * rs * rs) + s_in * (ms + 1)) \
+        + s * (4 * sum_i * ms + rs * 2 * ms + 2 * sum_i + rs) + rs * s_in * (ms + 1)
+    return float(flops.sum()), float(byts.sum())
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--B", type=int, default=4096)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on exactly one GPU: the batched streams are independent and this build "
+              "has no multi-GPU path (see DESIGN.md for how it would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2106_11594_amd import rg, workloads as W
+
+    t0 = time.time()
+    bt = W.batched(B=args.B, dtype="f32", store=np.float32)
+    print("generated %d streams, %d rows in %.1fs" % (bt.B, int(bt.ns.sum()), time.time() - t0),
+          file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    A = torch.from_numpy(bt.A).to(dev)
+    Y = torch.from_numpy(bt.Y).to(dev)
+    rp = torch.from_numpy(bt.row_ptr).to(dev)
+    ao = torch.from_numpy(bt.a_off).to(dev)
+    r_max = headroom(bt.ms, bt.rs)
+    h = rg.Batch(bt.ms, r_max=r_max, dtype="f32", eps=1e-3)
+    h.plan(bt.ns)
+    x = torch.empty(h.n_x, dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        h.reset()
+        if ev is not None:
+            ev[0].record(stream)
+        h.push(A, Y, rp, ao)
+        if ev is not None:
+            ev[1].record(stream)
+        h.solution(x)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print("warmup done", file=sys.stderr, flush=True)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for k in range(args.steps):
+        step(evs[k])
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms_step = start.elapsed_time(stop) / args.steps
+    push_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    rows = int(bt.ns.sum())
+    value = rows / (ms_step / 1e3)
+    print("timed %d steps: %.3f ms/step, push %.3f ms" % (args.steps, ms_step, push_ms), file=sys.stderr, flush=True)
+
+    xg = x.double().cpu().numpy()
+    ranks, flags = h.rank(), h.flags()
+    flops, byts = model(bt.ms, bt.rs, bt.ns)
+    achieved = byts / (push_ms / 1e3) / 1e9
+    roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+            "kernel": "k_push_generic (state streamed from L2/HBM)",
+            "algorithmic_bytes_per_launch": byts, "algorithmic_flops_per_launch": flops,
+            "alu_tflops": flops / (push_ms / 1e3) / 1e12, "alu_peak_tflops": PEAK_ALU_TFLOPS}
+
+    out = {"metric": METRIC, "value": value, "unit": "row-updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "batched uneven streams: B=%d, m~U{16..256}, r~U{4..m/2}, n~U{m..8m}, "
+                                  "FP32 state, FP64 rank test (eps 1e-3), rank capacity r+r/8+4" % bt.B,
+                      "streams": bt.B, "rows": rows},
+           "roofline": roof}
+
+    if not args.no_cpu:
+        from oracle import ref_c
+        ref_c.build()
+        nth = min(16, os.cpu_count() or 1)
+        Af = bt.A.astype(np.float64)
+        Yf = bt.Y.astype(np.float64)
+        order = np.argsort(-(bt.ns * bt.ms.astype(np.int64) * bt.rs)).astype(np.int64)
+        t1 = time.time()
+        Xo, xoff, ro, st, used = ref_c.solve_batch(bt.ms, bt.row_ptr, bt.a_off, Af, Yf, eps=1e-3, caps=r_max,
+                                                   order=order, nthreads=nth)
+        dt = time.time() - t1
+        out["cpu_baseline"] = {"value": rows / dt, "unit": "row-updates/s", "cores": int(used), "kind": "oracle",
+                               "sample": "the whole workload (all %d streams, %d rows), plain FP64 C "
+                                         "Algorithm 1, one thread per stream, %.1f s" % (bt.B, rows, dt)}
+        errs = np.empty(bt.B)
+        kap = np.empty(bt.B)
+        for b in range(bt.B):
+            o = xoff[b]
+            xo = Xo[o:o + bt.ms[b]]
+            errs[b] = np.linalg.norm(xg[o:o + bt.ms[b]] - xo) / max(np.linalg.norm(xo), 1e-300)
+            Ab, _ = bt.stream(b)
+            kap[b] = np.linalg.cond(Ab[:int(ro[b])].astype(np.float64)) if ro[b] > 0 else 1.0
+        good = kap <= 1e3
+        out["error"] = {"rank_match": int((ranks == ro).sum()), "streams": bt.B,
+                        "flags_nonzero": int((flags != 0).sum()),
+                        "rel_err_max": float(errs.max()), "rel_err_median": float(np.median(errs)),
+                        "rel_err_p99": float(np.percentile(errs, 99)),
+                        "rel_err_max_kappa_le_1e3": float(errs[good].max()) if good.any() else None,
+                        "streams_kappa_le_1e3": int(good.sum()),
+                        "streams_over_1e-5": int((errs > 1e-5).sum()),
+                        "kappa_of_streams_over_1e-5": sorted(float(k) for k in kap[errs > 1e-5])[:20],
+                        "bound": "1e-5 relative for kappa(C) <= 1e3, 0.1 kappa(C) 2^-23 above"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

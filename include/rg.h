@@ -1,0 +1,172 @@
+/*
+ * rg.h -- C ABI of librg.so: rank-Greville recursive least squares on
+ * MI355X (gfx950).
+ *
+ * The operation (Staub & Steinmann, "Efficient Recursive Least Squares Solver
+ * for Rank-Deficient Matrices"): a stream receives observation rows
+ * Gamma_i in R^m with targets y_i and keeps the minimum-norm least-squares
+ * solution x_n = A_n^+ Y_n of the rows seen so far (introduction, definition
+ * of the least-squares solution and its pseudoinverse form).  Each pushed row
+ * is one call of Algorithm 1 (UpdateLeastSquares): projection gamma = Ct Gamma,
+ * rejection Gamma_r = Gamma - C^T gamma, the rank test of Section 3, then the
+ * independent update (Theorems 4 and 6) or the dependent update (Theorems 5
+ * and 6).  The state is a full-rank factorisation: C (r x m, the accepted
+ * rows), its dual basis Ct = (C C^T)^-1 C and P^-1 = (B^T B)^-1 (Section 2.1),
+ * plus the solution in coordinates w = C x, so that x = Ct^T w.
+ *
+ * Conventions for every call:
+ *  - Pointers marked (device) are HIP device pointers; (host) are host
+ *    pointers.  The caller owns every buffer it passes and keeps it valid
+ *    until the handle's HIP stream has passed the call.
+ *  - Calls are ordered on the handle's HIP stream (rg_options.stream).  Only
+ *    rg_rank / rg_batch_rank / rg_status_flags / rg_batch_flags synchronise
+ *    that stream.
+ *  - All state lives in one device workspace allocated by rg_init /
+ *    rg_batch_init and freed by rg_destroy; pushes never allocate.
+ *  - Errors: invalid arguments return RG_E_INVALID and leave the state
+ *    untouched.  Conditions found on the device while rows are applied set a
+ *    sticky per-stream flag (RG_FLAG_*): that row and every later row of that
+ *    stream are ignored until rg_reset.  Pushes return RG_OK once the work is
+ *    enqueued; read the flags to learn what happened.  No C++ exception
+ *    crosses this boundary.
+ *  - Element types: RG_F32 streams take float rows/targets and keep C and Ct
+ *    in FP32, P^-1 in FP64 (FP32 Sherman-Morrison downdates lose positive
+ *    definiteness on ill-conditioned bases), and the rejection, its norm, the
+ *    rank decision, the Greville denominators, their reciprocals and w are
+ *    FP64.  RG_F64 streams take double inputs and keep everything in FP64.
+ */
+#ifndef RG_H
+#define RG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RG_OK = 0,
+    RG_E_INVALID = 1,       /* bad argument; nothing was done */
+    RG_E_NOMEM = 2,         /* device or host allocation failed (init only) */
+    RG_E_DEVICE = 3,        /* a HIP runtime call failed */
+    RG_E_UNSUPPORTED = 4    /* valid request outside this build's limits */
+} rg_status;
+
+typedef enum { RG_F32 = 0, RG_F64 = 1 } rg_dtype;
+
+/* Sticky per-stream flags, set on the device. */
+#define RG_FLAG_NONFINITE     0x1u  /* a row or target was NaN/Inf */
+#define RG_FLAG_RANK_CAPACITY 0x2u  /* an independent row arrived at r == r_max */
+#define RG_FLAG_DENOMINATOR   0x4u  /* 1 + gamma^T zeta not finite or <= 0 */
+
+/* Option bits. */
+#define RG_OPT_NO_REPROJECT   0x1u  /* skip the second projection pass of independent rows */
+#define RG_OPT_GENERIC_KERNEL 0x2u  /* force the global-memory kernel (testing) */
+
+typedef struct {
+    int32_t dtype;   /* rg_dtype */
+    int32_t r_max;   /* rank capacity per stream (<= m); <= 0 means m.  Used
+                        only by rg_init; rg_batch_init takes per-stream values */
+    double eps;      /* rank-test threshold of Section 3: a row is dependent
+                        iff ||Gamma_r|| < eps or ||Gamma_r|| < eps ||Gamma||.
+                        eps < 0 selects the default: for RG_F64 the paper's
+                        (m^2 r + m r + m) 2^-52 at the current rank r, for
+                        RG_F32 1e-3.  eps = 0 is the exact test Gamma_r == 0. */
+    void *stream;    /* hipStream_t for every call on the handle; NULL = null stream */
+    uint32_t flags;  /* RG_OPT_* */
+} rg_options;
+
+typedef struct rg_ctx *rg_handle;
+
+/* Fill *opt with the defaults (RG_F32, r_max = m, eps = -1, null stream). */
+void rg_default_options(rg_options *opt);
+
+/* ---- one stream -------------------------------------------------------- */
+
+/* Create a stream with m regressors (m >= 1) in the empty state (rank 0,
+ * x = 0, i.e. A_0^+ = 0).  opt may be NULL. */
+rg_status rg_init(rg_handle *out, int32_t m, const rg_options *opt);
+
+/* Push k >= 0 rows: gamma (device, k x m row-major, dtype of the handle),
+ * y (device, k).  Rows are applied in order, each as one call of
+ * Algorithm 1.  k = 0 is a no-op. */
+rg_status rg_push_rows(rg_handle h, const void *gamma, const void *y, int64_t k);
+
+/* Write x_n = Ct^T w (device, m elements of the handle's dtype). */
+rg_status rg_solution(rg_handle h, void *x);
+
+/* Current rank r (host).  Synchronises the handle's stream. */
+rg_status rg_rank(rg_handle h, int32_t *r);
+
+/* Sticky RG_FLAG_* bits (host).  Synchronises the handle's stream. */
+rg_status rg_status_flags(rg_handle h, uint32_t *flags);
+
+/* Back to the empty state (rank 0, x = 0, flags cleared); stream-ordered. */
+rg_status rg_reset(rg_handle h);
+
+/* Release the workspace.  Synchronises the handle's stream first. */
+rg_status rg_destroy(rg_handle h);
+
+/* ---- B independent streams --------------------------------------------- */
+
+/* Create B >= 1 streams; m (host, B) gives each stream's regressor count and
+ * r_max (host, B, nullable = m) its rank capacity.  opt->r_max is ignored.
+ * Streams are numbered 0..B-1 everywhere below. */
+rg_status rg_batch_init(rg_handle *out, int32_t B, const int32_t *m, const int32_t *r_max,
+                        const rg_options *opt);
+
+/* Push rows to every stream at once.  Stream b receives the rows
+ * row_ptr[b] .. row_ptr[b+1]-1 of the packed target vector y (device), and
+ * its rows start at element gamma_off[b] of gamma (device, each stream's
+ * rows row-major n_b x m_b).  row_ptr (device, B+1 int64, non-decreasing) and
+ * gamma_off (device, B int64) must describe in-bounds, non-overlapping rows:
+ * the library does not read them on the host.  Streams are processed
+ * concurrently in one persistent launch, largest expected cost first (see
+ * rg_batch_plan). */
+rg_status rg_batch_push(rg_handle h, const void *gamma, const void *y, const int64_t *row_ptr,
+                        const int64_t *gamma_off);
+
+/* Optional scheduling hint: rows_hint (host, B) = rows each stream will get
+ * per push.  Streams are then taken longest first by rows * m * r_max
+ * (default: m * m * r_max). */
+rg_status rg_batch_plan(rg_handle h, const int64_t *rows_hint);
+
+/* Write every x_b (device) packed back to back: x_b starts at element
+ * sum_{c<b} m_c. */
+rg_status rg_batch_solution(rg_handle h, void *x);
+
+/* Ranks (host, B int32).  Synchronises. */
+rg_status rg_batch_rank(rg_handle h, int32_t *r);
+
+/* Flags (host, B uint32).  Synchronises. */
+rg_status rg_batch_flags(rg_handle h, uint32_t *flags);
+
+/* Copy stream b's state to caller buffers (device; any may be NULL): C and
+ * Ct as r x m row-major in the handle dtype, Pinv as r x r row-major doubles,
+ * w as r doubles,
+ * where r is the current rank (read it first with rg_batch_rank).
+ * Synchronises the handle's stream; meant for tests and checkpoints. */
+rg_status rg_batch_get_state(rg_handle h, int32_t b, void *C, void *Ct, void *Pinv, double *w);
+
+/* Adjoint of the solve at constant rank (derivative of the rank-r truncated
+ * pseudoinverse, Golub-Pereyra) for a loss L(x): given g = dL/dx (device,
+ * packed like rg_batch_solution) and the rows A and targets Y that were
+ * pushed since the last reset (device, laid out as in rg_batch_push), write
+ * dL/dA (device, laid out like A) and dL/dY (device, laid out like Y):
+ *   dL/dY = A s,  dL/dA = -(A s) x^T + (Y - A x) s^T + (A t) p^T,
+ * with s = Ct^T P^-1 Ct g, t = Ct^T P^-1 Ct x, p = g - C^T Ct g, built from
+ * the maintained factorisation (A^+ A^+T = Ct^T P^-1 Ct, A^+ A = C^T Ct). */
+rg_status rg_batch_adjoint(rg_handle h, const void *A, const void *Y, const int64_t *row_ptr,
+                           const int64_t *a_off, const void *g, void *dA, void *dY);
+
+/* Device bytes the workspace of such a batch takes. */
+size_t rg_workspace_bytes(int32_t B, const int32_t *m, const int32_t *r_max, int32_t dtype);
+
+/* Static description of a status code. */
+const char *rg_status_string(rg_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RG_H */

@@ -1,0 +1,406 @@
+// Host side of librg.so: argument checks, the device workspace, scheduling
+// order and kernel launches.  See include/rg.h for the contract.
+#include "../../include/rg.h"
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "rg_internal.h"
+#include "rg_classes.h"
+
+using rg::StreamMeta;
+
+struct rg_ctx {
+    int B = 0;
+    int dtype = RG_F32;
+    size_t esize = 4;
+    hipStream_t stream = nullptr;
+    uint32_t opts = 0;
+    double eps = -1.0;
+    int device = 0;
+    int num_cus = 0;
+    void *ws = nullptr;          // one device allocation for everything below
+    size_t ws_bytes = 0;
+    StreamMeta *d_meta = nullptr;
+    int32_t *d_order = nullptr;  // B entries: generic-class streams first, then each size class
+    uint32_t *d_counter = nullptr;  // one queue head per kernel family (RG_MAX_FAMILIES)
+    void *d_state = nullptr;
+    double *d_p = nullptr;
+    double *d_w = nullptr;
+    std::vector<StreamMeta> h_meta;
+    std::vector<int64_t> cost;
+    // per-family segments of d_order
+    std::vector<int> fam_begin, fam_count;
+    int m_max_generic = 0, rmax_max_generic = 0;
+    int m_max_all = 0, rmax_max_all = 0;
+};
+
+namespace {
+
+#define HIPCHK(x)                                  \
+    do {                                           \
+        hipError_t e_ = (x);                       \
+        if (e_ != hipSuccess) return RG_E_DEVICE;  \
+    } while (0)
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Layout {
+    std::vector<StreamMeta> meta;
+    size_t state_elems = 0, p_elems = 0, w_elems = 0, x_elems = 0;
+};
+
+Layout plan_layout(int32_t B, const int32_t *m, const int32_t *r_max, size_t esize) {
+    Layout L;
+    L.meta.resize(B);
+    const size_t quantum = 16 / esize;  // keep every block 16-byte aligned
+    for (int b = 0; b < B; ++b) {
+        StreamMeta &M = L.meta[b];
+        M.m = m[b];
+        M.r_max = (r_max && r_max[b] > 0) ? std::min(r_max[b], m[b]) : m[b];
+        M.ldm = (int32_t)align_up((size_t)M.m, quantum);
+        M.r = 0;
+        M.flags = 0;
+        M.cls = -1;
+        M.state_off = (int64_t)L.state_elems;
+        L.state_elems += align_up(2 * (size_t)M.r_max * M.ldm, quantum);
+        M.p_off = (int64_t)L.p_elems;
+        L.p_elems += align_up((size_t)M.r_max * M.r_max, 2);
+        M.w_off = (int64_t)L.w_elems;
+        L.w_elems += align_up((size_t)M.r_max, 2);
+        M.x_off = (int64_t)L.x_elems;
+        L.x_elems += (size_t)M.m;
+        M.rows_seen = 0;
+    }
+    return L;
+}
+
+size_t ws_size(const Layout &L, int B, size_t esize) {
+    size_t off = align_up(sizeof(StreamMeta) * (size_t)B, 256);
+    off += align_up(sizeof(int32_t) * (size_t)B, 256);
+    off += 256;  // counters
+    off += align_up(L.state_elems * esize, 256);
+    off += align_up(L.p_elems * sizeof(double), 256);
+    off += align_up(L.w_elems * sizeof(double), 256);
+    return off;
+}
+
+// Assign kernel families and upload the processing order (longest first).
+rg_status upload_order(rg_ctx *h) {
+    const int B = h->B;
+    const int nfam = RG_MAX_FAMILIES;
+    std::vector<std::vector<int32_t>> fam(nfam);
+    for (int b = 0; b < B; ++b) {
+        const int f = h->h_meta[b].cls + 1;  // family 0 = generic
+        fam[f].push_back(b);
+    }
+    std::vector<int32_t> order;
+    order.reserve(B);
+    h->fam_begin.assign(nfam, 0);
+    h->fam_count.assign(nfam, 0);
+    for (int f = 0; f < nfam; ++f) {
+        std::stable_sort(fam[f].begin(), fam[f].end(),
+                         [&](int32_t a, int32_t c) { return h->cost[a] > h->cost[c]; });
+        h->fam_begin[f] = (int)order.size();
+        h->fam_count[f] = (int)fam[f].size();
+        order.insert(order.end(), fam[f].begin(), fam[f].end());
+    }
+    HIPCHK(hipMemcpyAsync(h->d_order, order.data(), sizeof(int32_t) * B, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return RG_OK;
+}
+
+template <typename T>
+rg_status push_impl(rg_ctx *h, const void *gamma, const void *y, const int64_t *row_ptr, const int64_t *goff,
+                    int64_t k_single) {
+    rg::PushArgs<T> a;
+    a.meta = h->d_meta;
+    a.state = (T *)h->d_state;
+    a.preg = h->d_p;
+    a.wreg = h->d_w;
+    a.gamma = (const T *)gamma;
+    a.y = (const T *)y;
+    a.row_ptr = row_ptr;
+    a.gamma_off = goff;
+    a.k_single = k_single;
+    a.eps = h->eps;
+    a.opts = h->opts;
+    HIPCHK(rg::launch_reset_counter(h->d_counter, h->stream));
+    // size-class families (register-resident kernels)
+    for (int f = 1; f < RG_MAX_FAMILIES; ++f) {
+        if (h->fam_count[f] == 0) continue;
+        a.order = h->d_order + h->fam_begin[f];
+        a.n_order = h->fam_count[f];
+        a.counter = h->d_counter + f;
+        HIPCHK(rg::launch_push_class<T>(f - 1, a, h->num_cus, h->stream));
+    }
+    if (h->fam_count[0] > 0) {
+        a.order = h->d_order + h->fam_begin[0];
+        a.n_order = h->fam_count[0];
+        a.counter = h->d_counter;
+        const size_t lds = sizeof(double) * (2 * (size_t)h->m_max_generic + 3 * (size_t)h->rmax_max_generic + 8);
+        int per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / lds));
+        int grid = std::min(h->fam_count[0], h->num_cus * per_cu);
+        HIPCHK(rg::launch_push_generic<T>(a, grid, h->m_max_generic, h->rmax_max_generic, h->stream));
+    }
+    return RG_OK;
+}
+
+bool valid_handle(rg_handle h) { return h != nullptr && h->ws != nullptr; }
+
+}  // namespace
+
+extern "C" {
+
+void rg_default_options(rg_options *opt) {
+    if (!opt) return;
+    opt->dtype = RG_F32;
+    opt->r_max = 0;
+    opt->eps = -1.0;
+    opt->stream = nullptr;
+    opt->flags = 0;
+}
+
+const char *rg_status_string(rg_status s) {
+    switch (s) {
+        case RG_OK: return "ok";
+        case RG_E_INVALID: return "invalid argument";
+        case RG_E_NOMEM: return "out of memory";
+        case RG_E_DEVICE: return "HIP runtime error";
+        case RG_E_UNSUPPORTED: return "unsupported size";
+    }
+    return "unknown status";
+}
+
+size_t rg_workspace_bytes(int32_t B, const int32_t *m, const int32_t *r_max, int32_t dtype) {
+    if (B <= 0 || !m || (dtype != RG_F32 && dtype != RG_F64)) return 0;
+    for (int b = 0; b < B; ++b)
+        if (m[b] <= 0) return 0;
+    const size_t es = dtype == RG_F64 ? 8 : 4;
+    Layout L = plan_layout(B, m, r_max, es);
+    return ws_size(L, B, es);
+}
+
+rg_status rg_batch_init(rg_handle *out, int32_t B, const int32_t *m, const int32_t *r_max, const rg_options *opt) {
+    if (!out) return RG_E_INVALID;
+    *out = nullptr;
+    if (B <= 0 || !m) return RG_E_INVALID;
+    rg_options o;
+    rg_default_options(&o);
+    if (opt) o = *opt;
+    if (o.dtype != RG_F32 && o.dtype != RG_F64) return RG_E_INVALID;
+    for (int b = 0; b < B; ++b) {
+        if (m[b] <= 0) return RG_E_INVALID;
+        if (r_max && r_max[b] > m[b]) return RG_E_INVALID;
+    }
+    rg_ctx *h = new (std::nothrow) rg_ctx();
+    if (!h) return RG_E_NOMEM;
+    h->B = B;
+    h->dtype = o.dtype;
+    h->esize = o.dtype == RG_F64 ? 8 : 4;
+    h->stream = (hipStream_t)o.stream;
+    h->opts = o.flags;
+    h->eps = o.eps >= 0.0 ? o.eps : (o.dtype == RG_F32 ? 1e-3 : -1.0);
+    if (hipGetDevice(&h->device) != hipSuccess ||
+        hipDeviceGetAttribute(&h->num_cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess) {
+        delete h;
+        return RG_E_DEVICE;
+    }
+    Layout L = plan_layout(B, m, r_max, h->esize);
+    h->h_meta = L.meta;
+    // kernel family per stream
+    for (int b = 0; b < B; ++b) {
+        StreamMeta &M = h->h_meta[b];
+        M.cls = (o.flags & RG_OPT_GENERIC_KERNEL) ? -1 : rg::choose_class(M.m, M.r_max, h->dtype);
+        if (M.cls < 0) {
+            h->m_max_generic = std::max(h->m_max_generic, M.m);
+            h->rmax_max_generic = std::max(h->rmax_max_generic, M.r_max);
+        }
+        h->m_max_all = std::max(h->m_max_all, M.m);
+        h->rmax_max_all = std::max(h->rmax_max_all, M.r_max);
+    }
+    if (sizeof(double) * (2 * (size_t)h->m_max_generic + 3 * (size_t)h->rmax_max_generic + 8) > 160 * 1024 ||
+        sizeof(double) * (5 * (size_t)h->m_max_all + 4 * (size_t)h->rmax_max_all) > 160 * 1024) {
+        delete h;
+        return RG_E_UNSUPPORTED;
+    }
+    h->ws_bytes = ws_size(L, B, h->esize);
+    if (hipMalloc(&h->ws, h->ws_bytes) != hipSuccess) {
+        h->ws = nullptr;
+        delete h;
+        return RG_E_NOMEM;
+    }
+    char *p = (char *)h->ws;
+    h->d_meta = (StreamMeta *)p;
+    p += align_up(sizeof(StreamMeta) * (size_t)B, 256);
+    h->d_order = (int32_t *)p;
+    p += align_up(sizeof(int32_t) * (size_t)B, 256);
+    h->d_counter = (uint32_t *)p;
+    p += 256;
+    h->d_state = p;
+    p += align_up(L.state_elems * h->esize, 256);
+    h->d_p = (double *)p;
+    p += align_up(L.p_elems * sizeof(double), 256);
+    h->d_w = (double *)p;
+    rg_status st = RG_OK;
+    if (hipMemsetAsync(h->ws, 0, h->ws_bytes, h->stream) != hipSuccess ||
+        hipMemcpyAsync(h->d_meta, h->h_meta.data(), sizeof(StreamMeta) * B, hipMemcpyHostToDevice, h->stream) !=
+            hipSuccess)
+        st = RG_E_DEVICE;
+    h->cost.resize(B);
+    for (int b = 0; b < B; ++b) h->cost[b] = (int64_t)h->h_meta[b].m * h->h_meta[b].m * h->h_meta[b].r_max;
+    if (st == RG_OK) st = upload_order(h);
+    if (st != RG_OK) {
+        (void)hipFree(h->ws);
+        delete h;
+        return st;
+    }
+    *out = h;
+    return RG_OK;
+}
+
+rg_status rg_init(rg_handle *out, int32_t m, const rg_options *opt) {
+    if (!out) return RG_E_INVALID;
+    *out = nullptr;
+    if (m <= 0) return RG_E_INVALID;
+    rg_options o;
+    rg_default_options(&o);
+    if (opt) o = *opt;
+    if (o.r_max > m) return RG_E_INVALID;
+    int32_t rm = o.r_max > 0 ? o.r_max : m;
+    return rg_batch_init(out, 1, &m, &rm, &o);
+}
+
+rg_status rg_batch_plan(rg_handle h, const int64_t *rows_hint) {
+    if (!valid_handle(h)) return RG_E_INVALID;
+    for (int b = 0; b < h->B; ++b) {
+        const StreamMeta &M = h->h_meta[b];
+        if (rows_hint && rows_hint[b] < 0) return RG_E_INVALID;
+        h->cost[b] = rows_hint ? rows_hint[b] * (int64_t)M.m * M.r_max : (int64_t)M.m * M.m * M.r_max;
+    }
+    return upload_order(h);
+}
+
+rg_status rg_push_rows(rg_handle h, const void *gamma, const void *y, int64_t k) {
+    if (!valid_handle(h) || h->B != 1 || k < 0) return RG_E_INVALID;
+    if (k == 0) return RG_OK;
+    if (!gamma || !y) return RG_E_INVALID;
+    return h->dtype == RG_F64 ? push_impl<double>(h, gamma, y, nullptr, nullptr, k)
+                              : push_impl<float>(h, gamma, y, nullptr, nullptr, k);
+}
+
+rg_status rg_batch_push(rg_handle h, const void *gamma, const void *y, const int64_t *row_ptr,
+                        const int64_t *gamma_off) {
+    if (!valid_handle(h) || !gamma || !y || !row_ptr || !gamma_off) return RG_E_INVALID;
+    return h->dtype == RG_F64 ? push_impl<double>(h, gamma, y, row_ptr, gamma_off, 0)
+                              : push_impl<float>(h, gamma, y, row_ptr, gamma_off, 0);
+}
+
+rg_status rg_batch_solution(rg_handle h, void *x) {
+    if (!valid_handle(h) || !x) return RG_E_INVALID;
+    hipError_t e = h->dtype == RG_F64
+                       ? rg::launch_solution<double>(h->d_meta, h->B, (const double *)h->d_state, h->d_w,
+                                                     (double *)x, h->stream)
+                       : rg::launch_solution<float>(h->d_meta, h->B, (const float *)h->d_state, h->d_w,
+                                                    (float *)x, h->stream);
+    return e == hipSuccess ? RG_OK : RG_E_DEVICE;
+}
+
+rg_status rg_solution(rg_handle h, void *x) {
+    if (!valid_handle(h) || h->B != 1) return RG_E_INVALID;
+    return rg_batch_solution(h, x);
+}
+
+static rg_status read_meta(rg_handle h, std::vector<StreamMeta> &dst) {
+    dst.resize(h->B);
+    HIPCHK(hipMemcpyAsync(dst.data(), h->d_meta, sizeof(StreamMeta) * h->B, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return RG_OK;
+}
+
+rg_status rg_batch_rank(rg_handle h, int32_t *r) {
+    if (!valid_handle(h) || !r) return RG_E_INVALID;
+    std::vector<StreamMeta> M;
+    rg_status st = read_meta(h, M);
+    if (st != RG_OK) return st;
+    for (int b = 0; b < h->B; ++b) r[b] = M[b].r;
+    return RG_OK;
+}
+
+rg_status rg_batch_flags(rg_handle h, uint32_t *flags) {
+    if (!valid_handle(h) || !flags) return RG_E_INVALID;
+    std::vector<StreamMeta> M;
+    rg_status st = read_meta(h, M);
+    if (st != RG_OK) return st;
+    for (int b = 0; b < h->B; ++b) flags[b] = M[b].flags;
+    return RG_OK;
+}
+
+rg_status rg_rank(rg_handle h, int32_t *r) {
+    if (!valid_handle(h) || h->B != 1) return RG_E_INVALID;
+    return rg_batch_rank(h, r);
+}
+
+rg_status rg_status_flags(rg_handle h, uint32_t *flags) {
+    if (!valid_handle(h) || h->B != 1) return RG_E_INVALID;
+    return rg_batch_flags(h, flags);
+}
+
+rg_status rg_reset(rg_handle h) {
+    if (!valid_handle(h)) return RG_E_INVALID;
+    return rg::launch_reset_streams(h->d_meta, h->B, h->stream) == hipSuccess ? RG_OK : RG_E_DEVICE;
+}
+
+rg_status rg_batch_get_state(rg_handle h, int32_t b, void *C, void *Ct, void *Pinv, double *w) {
+    if (!valid_handle(h) || b < 0 || b >= h->B) return RG_E_INVALID;
+    std::vector<StreamMeta> M;
+    rg_status st = read_meta(h, M);
+    if (st != RG_OK) return st;
+    const StreamMeta &S = M[b];
+    if (S.r == 0) return RG_OK;
+    const size_t es = h->esize;
+    char *base = (char *)h->d_state + (size_t)S.state_off * es;
+    const size_t pitch = (size_t)S.ldm * es;
+    if (C) HIPCHK(hipMemcpy2DAsync(C, (size_t)S.m * es, base, pitch, (size_t)S.m * es, S.r, hipMemcpyDeviceToDevice,
+                                   h->stream));
+    if (Ct)
+        HIPCHK(hipMemcpy2DAsync(Ct, (size_t)S.m * es, base + (size_t)S.r_max * pitch, pitch, (size_t)S.m * es, S.r,
+                                hipMemcpyDeviceToDevice, h->stream));
+    if (Pinv)
+        HIPCHK(hipMemcpy2DAsync(Pinv, (size_t)S.r * sizeof(double), h->d_p + S.p_off, (size_t)S.r_max * sizeof(double),
+                                (size_t)S.r * sizeof(double), S.r, hipMemcpyDeviceToDevice, h->stream));
+    if (w)
+        HIPCHK(hipMemcpyAsync(w, h->d_w + S.w_off, sizeof(double) * S.r, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return RG_OK;
+}
+
+rg_status rg_batch_adjoint(rg_handle h, const void *A, const void *Y, const int64_t *row_ptr, const int64_t *a_off,
+                           const void *g, void *dA, void *dY) {
+    if (!valid_handle(h) || !A || !Y || !row_ptr || !a_off || !g || !dA || !dY) return RG_E_INVALID;
+    hipError_t e =
+        h->dtype == RG_F64
+            ? rg::launch_adjoint<double>(h->d_meta, h->B, (const double *)h->d_state, h->d_p, h->d_w,
+                                         (const double *)A, (const double *)Y, row_ptr, a_off, (const double *)g,
+                                         (double *)dA, (double *)dY, h->m_max_all, h->rmax_max_all, h->stream)
+            : rg::launch_adjoint<float>(h->d_meta, h->B, (const float *)h->d_state, h->d_p, h->d_w,
+                                        (const float *)A, (const float *)Y, row_ptr, a_off, (const float *)g,
+                                        (float *)dA, (float *)dY, h->m_max_all, h->rmax_max_all, h->stream);
+    return e == hipSuccess ? RG_OK : RG_E_DEVICE;
+}
+
+rg_status rg_destroy(rg_handle h) {
+    if (!h) return RG_E_INVALID;
+    rg_status st = RG_OK;
+    if (h->ws) {
+        if (hipStreamSynchronize(h->stream) != hipSuccess) st = RG_E_DEVICE;
+        if (hipFree(h->ws) != hipSuccess) st = RG_E_DEVICE;
+    }
+    delete h;
+    return st;
+}
+
+}  // extern "C"

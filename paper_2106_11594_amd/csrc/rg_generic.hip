@@ -1,0 +1,397 @@
+// Generic rank-Greville kernels for gfx950: state read and written in global
+// memory (L2 / HBM), any m and r_max that fit the LDS work vectors.
+//
+// One workgroup (4 wave64) owns one stream at a time and walks its rows in
+// order; workgroups take streams from a device-side queue (largest first).
+// Per row, following Algorithm 1 (UpdateLeastSquares):
+//   gamma   = Ct Gamma                 one wave per row k of Ct, lanes over j
+//   Gamma_r = Gamma - C^T gamma        one thread per column j, FP64 sum
+//   rank test of Section 3 on ||Gamma_r|| (FP64), uniform per workgroup
+//   independent (Theorems 4, 6): optional second projection pass,
+//       K = Gamma_r / ||Gamma_r||^2, Ct <- [Ct - gamma K^T; K^T],
+//       C <- [C; Gamma^T], P^-1 <- diag(P^-1, 1), w <- [w; y]
+//   dependent (Theorems 5, 6): zeta = P^-1 gamma, d = 1 + gamma^T zeta,
+//       P^-1 <- P^-1 - zeta zeta^T / d, w <- w + zeta (y - gamma^T w) / d
+// The solution is kept in coordinates w = C x (x = Ct^T w because
+// Ct C^T = I), which removes the pass over Ct that forms the dependent-case
+// gain K = Ct^T zeta / d; x is formed on demand by the solution kernel.
+#include "rg_internal.h"
+
+namespace rg {
+namespace {
+
+constexpr int NT = 256;
+constexpr int NW = NT / 64;
+
+// Accumulation type of gamma = Ct Gamma and zeta = P^-1 gamma.  FP64 for both
+// state types: with FP32 accumulation the x error roughly doubles on poorly
+// conditioned bases (measured against the FP64 oracle).
+template <typename T> struct AccG { using type = double; };
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum a and b over the workgroup; every thread gets the totals.  Fixed
+// order, so the result does not depend on scheduling.
+__device__ inline void block_sum2(double &a, double &b, double *sRed) {
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) {
+        sRed[2 * wid] = a;
+        sRed[2 * wid + 1] = b;
+    }
+    __syncthreads();
+    a = 0.0;
+    b = 0.0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        a += sRed[2 * i];
+        b += sRed[2 * i + 1];
+    }
+}
+
+// dst[k] = sum_j Ct[k][j] v[j] for k < r.
+template <typename T, typename Acc>
+__device__ inline void project(const T *Ct, int ldm, const double *v, double *dst, int r, int m) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int k = wid; k < r; k += NW) {
+        const T *row = Ct + (size_t)k * ldm;
+        Acc acc = 0;
+        for (int j = lane; j < m; j += 64) acc += (Acc)row[j] * (Acc)v[j];
+        acc = wave_sum(acc);
+        if (lane == 0) dst[k] = (double)acc;
+    }
+}
+
+// out[j] = v[j] - sum_k C[k][j] g[k] in FP64; returns this thread's share of
+// sum_j out[j]^2 (out may alias v).
+template <typename T>
+__device__ inline double reject(const T *C, int ldm, const double *v, const double *g, double *out, int r,
+                                int m) {
+    double s = 0.0;
+    for (int j = threadIdx.x; j < m; j += NT) {
+        double acc = v[j];
+        for (int k = 0; k < r; ++k) acc -= (double)C[(size_t)k * ldm + j] * g[k];
+        out[j] = acc;
+        s += acc * acc;
+    }
+    return s;
+}
+
+template <typename T>
+__device__ void run_stream(const PushArgs<T> &a, int b, double *sG, double *sGr, double *sGam, double *sGam2,
+                           double *sZ, double *sRed) {
+    StreamMeta *M = a.meta + b;
+    const int m = M->m, rmax = M->r_max, ldm = M->ldm;
+    int r = M->r;
+    uint32_t flags = M->flags;
+    T *C = a.state + M->state_off;
+    T *Ct = C + (size_t)rmax * ldm;
+    double *P = a.preg + M->p_off;
+    double *w = a.wreg + M->w_off;
+    int64_t i0, i1, goff;
+    if (a.row_ptr) {
+        i0 = a.row_ptr[b];
+        i1 = a.row_ptr[b + 1];
+        goff = a.gamma_off[b];
+    } else {
+        i0 = 0;
+        i1 = a.k_single;
+        goff = 0;
+    }
+    const int tid = threadIdx.x;
+    int64_t applied = 0;
+    using Acc = typename AccG<T>::type;
+    for (int64_t i = i0; i < i1 && flags == 0; ++i) {
+        const T *G = a.gamma + goff + (i - i0) * (int64_t)m;
+        double g2 = 0.0, bad = 0.0;
+        for (int j = tid; j < m; j += NT) {
+            const double g = (double)G[j];
+            sG[j] = g;
+            g2 += g * g;
+            if (!isfinite(g)) bad = 1.0;
+        }
+        const double yv = (double)a.y[i];
+        block_sum2(g2, bad, sRed);
+        if (bad != 0.0 || !isfinite(yv)) {
+            flags |= FLAG_NONFINITE;
+            break;
+        }
+        project<T, Acc>(Ct, ldm, sG, sGam, r, m);
+        __syncthreads();
+        double s = reject(C, ldm, sG, sGam, sGr, r, m), unused = 0.0;
+        block_sum2(s, unused, sRed);
+        const double eps = a.eps >= 0.0 ? a.eps
+                                        : ((double)m * m * r + (double)m * r + (double)m) * 0x1p-52;
+        const double nr = sqrt(s), ng = sqrt(g2);
+        const bool dependent = (s == 0.0) || (nr < eps) || (nr < eps * ng);
+        if (!dependent) {
+            if (r == rmax) {
+                flags |= FLAG_RANK_CAPACITY;
+                break;
+            }
+            if (!(a.opts & OPT_NO_REPROJECT) && r > 0) {
+                // second pass ("twice is enough"): gamma2 = Ct Gamma_r, Gamma_r -= C^T gamma2;
+                // zero in exact arithmetic, it removes the rounding left in Gamma_r.
+                project<T, Acc>(Ct, ldm, sGr, sGam2, r, m);
+                __syncthreads();
+                s = reject(C, ldm, sGr, sGam2, sGr, r, m);
+                unused = 0.0;
+                block_sum2(s, unused, sRed);
+                for (int k = tid; k < r; k += NT) sGam[k] += sGam2[k];
+                __syncthreads();
+            }
+            const double inv_s = 1.0 / s;
+            for (int j = tid; j < m; j += NT) {
+                const double K = sGr[j] * inv_s;
+                if constexpr (sizeof(T) == 4) {
+                    const float Kf = (float)K;
+                    for (int k = 0; k < r; ++k) {
+                        float &c = Ct[(size_t)k * ldm + j];
+                        c = fmaf(-(float)sGam[k], Kf, c);
+                    }
+                } else {
+                    for (int k = 0; k < r; ++k) {
+                        double &c = Ct[(size_t)k * ldm + j];
+                        c = fma(-sGam[k], K, c);
+                    }
+                }
+                Ct[(size_t)r * ldm + j] = (T)K;
+                C[(size_t)r * ldm + j] = (T)sG[j];
+            }
+            for (int k = tid; k < r; k += NT) {
+                P[(size_t)r * rmax + k] = 0.0;
+                P[(size_t)k * rmax + r] = 0.0;
+            }
+            if (tid == 0) {
+                P[(size_t)r * rmax + r] = 1.0;
+                w[r] = yv;
+            }
+            r += 1;
+        } else if (r > 0) {
+            // zeta_i = sum_k P[k][i] gamma_k  (P^-1 is symmetric; column reads coalesce)
+            for (int ii = tid; ii < r; ii += NT) {
+                double acc = 0.0;
+                for (int k = 0; k < r; ++k) acc += P[(size_t)k * rmax + ii] * sGam[k];
+                sZ[ii] = acc;
+            }
+            __syncthreads();
+            double gz = 0.0, gw = 0.0;
+            for (int k = tid; k < r; k += NT) {
+                gz += sGam[k] * sZ[k];
+                gw += sGam[k] * w[k];
+            }
+            block_sum2(gz, gw, sRed);
+            const double d = 1.0 + gz;
+            if (!(d > 0.0) || !isfinite(d)) {
+                flags |= FLAG_DENOMINATOR;
+                break;
+            }
+            const double inv_d = 1.0 / d;
+            const double dy = yv - gw;
+            // P^-1 <- P^-1 - zeta zeta^T / d (FP64; the product order keeps it exactly symmetric)
+            const int rr = r * r;
+            for (int idx = tid; idx < rr; idx += NT) {
+                const int ii = idx / r, k = idx - ii * r;
+                P[(size_t)ii * rmax + k] -= (sZ[ii] * sZ[k]) * inv_d;
+            }
+            for (int k = tid; k < r; k += NT) w[k] += sZ[k] * (dy * inv_d);
+        }
+        ++applied;
+        __syncthreads();
+    }
+    __syncthreads();
+    if (tid == 0) {
+        M->r = r;
+        M->flags = flags;
+        M->rows_seen += applied;
+    }
+    // Keep a barrier between these thread-0 stores and the thread-0 queue pop
+    // at the top of the caller's loop: without it the compiler may merge the
+    // two thread-0 regions across the loop back-edge, which gives the loop a
+    // second entry at the barrier and lets the other threads loop without the
+    // pop (the queue head then never advances).
+    __syncthreads();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NT) k_push_generic(PushArgs<T> a, int m_max, int r_max_max) {
+    extern __shared__ double smem[];
+    double *sG = smem;
+    double *sGr = sG + m_max;
+    double *sGam = sGr + m_max;
+    double *sGam2 = sGam + r_max_max;
+    double *sZ = sGam2 + r_max_max;
+    double *sRed = sZ + r_max_max;
+    __shared__ int s_idx;
+    for (;;) {
+        if (threadIdx.x == 0) s_idx = (int)atomicAdd(a.counter, 1u);
+        __syncthreads();
+        const int idx = s_idx;
+        __syncthreads();
+        if (idx >= a.n_order) break;
+        const int b = a.order[idx];
+        if (a.meta[b].cls < 0) run_stream<T>(a, b, sG, sGr, sGam, sGam2, sZ, sRed);
+    }
+}
+
+__global__ void k_reset_counter(uint32_t *c) {
+    if (threadIdx.x < 64) c[threadIdx.x] = 0u;  // the 256-byte counter block
+}
+
+__global__ void k_reset_streams(StreamMeta *meta, int B) {
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < B; b += gridDim.x * blockDim.x) {
+        meta[b].r = 0;
+        meta[b].flags = 0u;
+        meta[b].rows_seen = 0;
+    }
+}
+
+// x_b = Ct_b^T w_b, FP64 sums, one workgroup per stream.
+template <typename T>
+__global__ void __launch_bounds__(NT) k_solution(const StreamMeta *meta, const T *state, const double *wreg, T *x) {
+    const StreamMeta M = meta[blockIdx.x];
+    const T *Ct = state + M.state_off + (size_t)M.r_max * M.ldm;
+    const double *w = wreg + M.w_off;
+    for (int j = threadIdx.x; j < M.m; j += NT) {
+        double acc = 0.0;
+        for (int k = 0; k < M.r; ++k) acc += (double)Ct[(size_t)k * M.ldm + j] * w[k];
+        x[M.x_off + j] = (T)acc;
+    }
+}
+
+// Adjoint at constant rank, one workgroup per stream.  Preamble (O(r m)):
+//   x = Ct^T w, u = Ct g, v = Ct x, s = Ct^T P^-1 u, t = Ct^T P^-1 v, p = g - C^T u;
+// then one pass over the rows of A: a_i = A_i s, b_i = A_i t, rho_i = Y_i - A_i x,
+//   dY_i = a_i, dA_i = -a_i x + rho_i s + b_i p.
+template <typename T>
+__global__ void __launch_bounds__(NT) k_adjoint(const StreamMeta *meta, const T *state, const double *preg,
+                                                const double *wreg, const T *A, const T *Y, const int64_t *row_ptr,
+                                                const int64_t *a_off, const T *g, T *dA, T *dY, int m_max,
+                                                int r_max_max) {
+    extern __shared__ double smem[];
+    const int b = blockIdx.x;
+    const StreamMeta M = meta[b];
+    const int m = M.m, r = M.r, ldm = M.ldm, rmax = M.r_max;
+    const T *C = state + M.state_off;
+    const T *Ct = C + (size_t)rmax * ldm;
+    const double *P = preg + M.p_off;
+    const double *w = wreg + M.w_off;
+    double *sx = smem, *sg = sx + m_max, *ss = sg + m_max, *st = ss + m_max, *sp = st + m_max;
+    double *su = sp + m_max, *sv = su + r_max_max, *su2 = sv + r_max_max, *sv2 = su2 + r_max_max;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    for (int j = tid; j < m; j += NT) {
+        double acc = 0.0;
+        for (int k = 0; k < r; ++k) acc += (double)Ct[(size_t)k * ldm + j] * w[k];
+        sx[j] = acc;
+        sg[j] = (double)g[M.x_off + j];
+    }
+    __syncthreads();
+    project<T, double>(Ct, ldm, sg, su, r, m);
+    project<T, double>(Ct, ldm, sx, sv, r, m);
+    __syncthreads();
+    for (int i = tid; i < r; i += NT) {
+        double a1 = 0.0, a2 = 0.0;
+        for (int k = 0; k < r; ++k) {
+            const double pk = P[(size_t)k * rmax + i];
+            a1 += pk * su[k];
+            a2 += pk * sv[k];
+        }
+        su2[i] = a1;
+        sv2[i] = a2;
+    }
+    __syncthreads();
+    for (int j = tid; j < m; j += NT) {
+        double a1 = 0.0, a2 = 0.0, a3 = sg[j];
+        for (int k = 0; k < r; ++k) {
+            const double ct = (double)Ct[(size_t)k * ldm + j];
+            a1 += ct * su2[k];
+            a2 += ct * sv2[k];
+            a3 -= (double)C[(size_t)k * ldm + j] * su[k];
+        }
+        ss[j] = a1;
+        st[j] = a2;
+        sp[j] = a3;
+    }
+    __syncthreads();
+    const int64_t i0 = row_ptr[b], i1 = row_ptr[b + 1];
+    const T *Ab = A + a_off[b];
+    T *dAb = dA + a_off[b];
+    for (int64_t i = i0 + wid; i < i1; i += NW) {
+        const T *row = Ab + (i - i0) * (int64_t)m;
+        double ca = 0.0, cb = 0.0, cx = 0.0;
+        for (int j = lane; j < m; j += 64) {
+            const double v = (double)row[j];
+            ca += v * ss[j];
+            cb += v * st[j];
+            cx += v * sx[j];
+        }
+        ca = wave_sum(ca);
+        cb = wave_sum(cb);
+        cx = wave_sum(cx);
+        const double rho = (double)Y[i] - cx;
+        T *drow = dAb + (i - i0) * (int64_t)m;
+        for (int j = lane; j < m; j += 64) drow[j] = (T)(-ca * sx[j] + rho * ss[j] + cb * sp[j]);
+        if (lane == 0) dY[i] = (T)ca;
+    }
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_push_generic(const PushArgs<T> &a, int grid, int m_max, int r_max_max, hipStream_t s) {
+    const size_t lds = sizeof(double) * (2 * (size_t)m_max + 3 * (size_t)r_max_max + 2 * NW);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_push_generic<T>, dim3(grid), dim3(NT), lds, s, a, m_max, r_max_max);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_counter(uint32_t *counter, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_streams(StreamMeta *meta, int B, hipStream_t s) {
+    const int grid = (B + 255) / 256;
+    hipLaunchKernelGGL(k_reset_streams, dim3(grid), dim3(256), 0, s, meta, B);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_solution(const StreamMeta *meta, int B, const T *state, const double *wreg, T *x,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_solution<T>, dim3(B), dim3(NT), 0, s, meta, state, wreg, x);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adjoint(const StreamMeta *meta, int B, const T *state, const double *preg, const double *wreg,
+                          const T *A, const T *Y, const int64_t *row_ptr, const int64_t *a_off, const T *g, T *dA,
+                          T *dY, int m_max, int r_max_max, hipStream_t s) {
+    const size_t lds = sizeof(double) * (5 * (size_t)m_max + 4 * (size_t)r_max_max);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_adjoint<T>, dim3(B), dim3(NT), lds, s, meta, state, preg, wreg, A, Y, row_ptr, a_off, g,
+                       dA, dY, m_max, r_max_max);
+    return hipGetLastError();
+}
+
+template hipError_t launch_push_generic<float>(const PushArgs<float> &, int, int, int, hipStream_t);
+template hipError_t launch_push_generic<double>(const PushArgs<double> &, int, int, int, hipStream_t);
+template hipError_t launch_solution<float>(const StreamMeta *, int, const float *, const double *, float *,
+                                           hipStream_t);
+template hipError_t launch_solution<double>(const StreamMeta *, int, const double *, const double *, double *,
+                                            hipStream_t);
+template hipError_t launch_adjoint<float>(const StreamMeta *, int, const float *, const double *, const double *,
+                                          const float *, const float *, const int64_t *, const int64_t *,
+                                          const float *, float *, float *, int, int, hipStream_t);
+template hipError_t launch_adjoint<double>(const StreamMeta *, int, const double *, const double *,
+                                           const double *, const double *, const double *, const int64_t *,
+                                           const int64_t *, const double *, double *, double *, int, int,
+                                           hipStream_t);
+
+}  // namespace rg

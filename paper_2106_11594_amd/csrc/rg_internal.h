@@ -1,0 +1,60 @@
+// Internal declarations shared by the host API (rg_api.hip) and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace rg {
+
+// One record per stream, resident in device memory.
+struct StreamMeta {
+    int32_t m;          // regressors
+    int32_t r_max;      // rank capacity (rows reserved for C and Ct)
+    int32_t ldm;        // leading dimension of C and Ct rows (elements)
+    int32_t r;          // current rank
+    uint32_t flags;     // sticky RG_FLAG_* bits
+    int32_t cls;        // kernel size class chosen at init (-1: generic kernel)
+    int64_t state_off;  // element offset of C in the state region; Ct follows at +r_max*ldm
+    int64_t p_off;      // offset of P^-1 (doubles, r_max x r_max, row-major) in the P region
+    int64_t w_off;      // offset of w (doubles) in the w region
+    int64_t x_off;      // offset of x in packed solution vectors
+    int64_t rows_seen;  // rows applied since the last reset
+};
+
+constexpr uint32_t FLAG_NONFINITE = 0x1u;
+constexpr uint32_t FLAG_RANK_CAPACITY = 0x2u;
+constexpr uint32_t FLAG_DENOMINATOR = 0x4u;
+constexpr uint32_t OPT_NO_REPROJECT = 0x1u;
+
+// Arguments of a push launch (by value).
+template <typename T>
+struct PushArgs {
+    StreamMeta *meta;
+    const int32_t *order;    // processing order (stream ids), length n_order
+    int32_t n_order;
+    uint32_t *counter;       // work-queue head, zeroed before the launch
+    T *state;
+    double *preg;            // P^-1 blocks (FP64 for both state types)
+    double *wreg;
+    const T *gamma;
+    const T *y;
+    const int64_t *row_ptr;  // nullable: single stream with k_single rows
+    const int64_t *gamma_off;
+    int64_t k_single;
+    double eps;              // < 0: default of Section 3 at the current rank
+    uint32_t opts;
+};
+
+// Host-side launchers (defined in the kernel sources).
+template <typename T>
+hipError_t launch_push_generic(const PushArgs<T> &a, int grid, int m_max, int r_max_max, hipStream_t s);
+hipError_t launch_reset_counter(uint32_t *counter, hipStream_t s);
+hipError_t launch_reset_streams(StreamMeta *meta, int B, hipStream_t s);
+template <typename T>
+hipError_t launch_solution(const StreamMeta *meta, int B, const T *state, const double *wreg, T *x,
+                           hipStream_t s);
+template <typename T>
+hipError_t launch_adjoint(const StreamMeta *meta, int B, const T *state, const double *preg, const double *wreg,
+                          const T *A, const T *Y, const int64_t *row_ptr, const int64_t *a_off, const T *g, T *dA,
+                          T *dY, int m_max, int r_max_max, hipStream_t s);
+
+}  // namespace rg

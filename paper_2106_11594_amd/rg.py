@@ -1,0 +1,281 @@
+"""Python binding of librg.so (see include/rg.h).
+
+Argument marshalling only: every step of the update runs in the HIP kernels
+behind the C ABI.  torch supplies device memory and the HIP stream.  Loading
+fails loudly when the library has not been built
+(``python -m paper_2106_11594_amd.build``); there is no fallback path.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librg.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "rg.h")
+
+RG_F32, RG_F64 = 0, 1
+FLAG_NONFINITE, FLAG_RANK_CAPACITY, FLAG_DENOMINATOR = 0x1, 0x2, 0x4
+OPT_NO_REPROJECT, OPT_GENERIC_KERNEL = 0x1, 0x2
+_STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "HIP runtime error", 4: "unsupported size"}
+
+
+class RGError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__("%s failed: %s (status %d)" % (what, _STATUS.get(code, "?"), code))
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("r_max", ctypes.c_int32), ("eps", ctypes.c_double),
+                ("stream", ctypes.c_void_p), ("flags", ctypes.c_uint32)]
+
+
+_lib = None
+_p = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+
+_SIGS = {
+    "rg_default_options": (None, [_p]),
+    "rg_init": (ctypes.c_int, [_p, _i32, _p]),
+    "rg_push_rows": (ctypes.c_int, [_p, _p, _p, _i64]),
+    "rg_solution": (ctypes.c_int, [_p, _p]),
+    "rg_rank": (ctypes.c_int, [_p, _p]),
+    "rg_status_flags": (ctypes.c_int, [_p, _p]),
+    "rg_reset": (ctypes.c_int, [_p]),
+    "rg_destroy": (ctypes.c_int, [_p]),
+    "rg_batch_init": (ctypes.c_int, [_p, _i32, _p, _p, _p]),
+    "rg_batch_push": (ctypes.c_int, [_p, _p, _p, _p, _p]),
+    "rg_batch_plan": (ctypes.c_int, [_p, _p]),
+    "rg_batch_solution": (ctypes.c_int, [_p, _p]),
+    "rg_batch_rank": (ctypes.c_int, [_p, _p]),
+    "rg_batch_flags": (ctypes.c_int, [_p, _p]),
+    "rg_batch_get_state": (ctypes.c_int, [_p, _i32, _p, _p, _p, _p]),
+    "rg_batch_adjoint": (ctypes.c_int, [_p, _p, _p, _p, _p, _p, _p, _p]),
+    "rg_workspace_bytes": (ctypes.c_size_t, [_i32, _p, _p, _i32]),
+    "rg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+}
+
+
+def header_functions():
+    """Names of the functions declared in include/rg.h."""
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:[\w\s\*]+?)\b(rg_\w+)\s*\(", src, flags=re.M)))
+
+
+def lib():
+    """Load librg.so once (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("librg.so is not built; run `python -m paper_2106_11594_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code, what):
+    if code != 0:
+        raise RGError(code, what)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(dtype):
+    torch = _torch()
+    if dtype in ("f32", np.float32, torch.float32):
+        return RG_F32, torch.float32
+    if dtype in ("f64", np.float64, torch.float64):
+        return RG_F64, torch.float64
+    raise ValueError("dtype must be float32 or float64")
+
+
+def _dev(t, dtype, what, numel=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError("%s must be a CUDA (HIP) tensor" % what)
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError("%s must have dtype %s" % (what, dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % what)
+    if numel is not None and t.numel() != numel:
+        raise ValueError("%s must have %d elements" % (what, numel))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Batch:
+    """B independent recursive least-squares streams (rg_batch_* calls)."""
+
+    def __init__(self, ms, r_max=None, dtype="f32", eps=None, stream=None, flags=0):
+        torch = _torch()
+        L = lib()
+        self.code, self.tdtype = _dtype_code(dtype)
+        self.ms = np.ascontiguousarray(ms, dtype=np.int32).reshape(-1)
+        self.B = int(self.ms.shape[0])
+        self.r_max = None if r_max is None else np.ascontiguousarray(r_max, dtype=np.int32).reshape(-1)
+        self.x_off = np.zeros(self.B, dtype=np.int64)
+        self.x_off[1:] = np.cumsum(self.ms[:-1].astype(np.int64))
+        self.n_x = int(self.ms.astype(np.int64).sum())
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.torch_stream = stream
+        opt = Options()
+        L.rg_default_options(ctypes.byref(opt))
+        opt.dtype = self.code
+        opt.eps = -1.0 if eps is None else float(eps)
+        opt.stream = ctypes.c_void_p(stream.cuda_stream)
+        opt.flags = int(flags)
+        self._opt = opt
+        h = ctypes.c_void_p()
+        rp = None if self.r_max is None else self.r_max.ctypes.data_as(_p)
+        _check(L.rg_batch_init(ctypes.byref(h), self.B, self.ms.ctypes.data_as(_p), rp, ctypes.byref(opt)),
+               "rg_batch_init")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def plan(self, rows_hint=None):
+        rh = None if rows_hint is None else np.ascontiguousarray(rows_hint, dtype=np.int64)
+        _check(lib().rg_batch_plan(self._h, None if rh is None else rh.ctypes.data_as(_p)), "rg_batch_plan")
+
+    def push(self, gamma, y, row_ptr, gamma_off):
+        torch = _torch()
+        _check(lib().rg_batch_push(self._h, _dev(gamma, self.tdtype, "gamma"), _dev(y, self.tdtype, "y"),
+                                   _dev(row_ptr, torch.int64, "row_ptr", self.B + 1),
+                                   _dev(gamma_off, torch.int64, "gamma_off", self.B)), "rg_batch_push")
+
+    def solution(self, out=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty(self.n_x, dtype=self.tdtype, device="cuda")
+        _check(lib().rg_batch_solution(self._h, _dev(out, self.tdtype, "x", self.n_x)), "rg_batch_solution")
+        return out
+
+    def rank(self):
+        r = np.zeros(self.B, dtype=np.int32)
+        _check(lib().rg_batch_rank(self._h, r.ctypes.data_as(_p)), "rg_batch_rank")
+        return r
+
+    def flags(self):
+        f = np.zeros(self.B, dtype=np.uint32)
+        _check(lib().rg_batch_flags(self._h, f.ctypes.data_as(_p)), "rg_batch_flags")
+        return f
+
+    def reset(self):
+        _check(lib().rg_reset(self._h), "rg_reset")
+
+    def get_state(self, b):
+        """(C, Ct, Pinv, w) of stream b as device tensors (rank-sized)."""
+        torch = _torch()
+        r = int(self.rank()[b])
+        m = int(self.ms[b])
+        C = torch.empty((r, m), dtype=self.tdtype, device="cuda")
+        Ct = torch.empty((r, m), dtype=self.tdtype, device="cuda")
+        P = torch.empty((r, r), dtype=torch.float64, device="cuda")
+        w = torch.empty(r, dtype=torch.float64, device="cuda")
+        if r:
+            _check(lib().rg_batch_get_state(self._h, int(b), _dev(C, None, "C"), _dev(Ct, None, "Ct"),
+                                            _dev(P, None, "P"), _dev(w, None, "w")), "rg_batch_get_state")
+        return C, Ct, P, w
+
+    def adjoint(self, A, Y, row_ptr, a_off, g, dA=None, dY=None):
+        torch = _torch()
+        if dA is None:
+            dA = torch.empty_like(A)
+        if dY is None:
+            dY = torch.empty_like(Y)
+        _check(lib().rg_batch_adjoint(self._h, _dev(A, self.tdtype, "A"), _dev(Y, self.tdtype, "Y"),
+                                      _dev(row_ptr, torch.int64, "row_ptr", self.B + 1),
+                                      _dev(a_off, torch.int64, "a_off", self.B),
+                                      _dev(g, self.tdtype, "g", self.n_x),
+                                      _dev(dA, self.tdtype, "dA", A.numel()),
+                                      _dev(dY, self.tdtype, "dY", Y.numel())), "rg_batch_adjoint")
+        return dA, dY
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(lib().rg_destroy(self._h), "rg_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Solver:
+    """One stream: rg_init / rg_push_rows / rg_solution / rg_rank."""
+
+    def __init__(self, m, r_max=None, dtype="f32", eps=None, stream=None, flags=0):
+        torch = _torch()
+        L = lib()
+        self.code, self.tdtype = _dtype_code(dtype)
+        self.m = int(m)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        opt = Options()
+        L.rg_default_options(ctypes.byref(opt))
+        opt.dtype = self.code
+        opt.r_max = 0 if r_max is None else int(r_max)
+        opt.eps = -1.0 if eps is None else float(eps)
+        opt.stream = ctypes.c_void_p(stream.cuda_stream)
+        opt.flags = int(flags)
+        h = ctypes.c_void_p()
+        _check(L.rg_init(ctypes.byref(h), self.m, ctypes.byref(opt)), "rg_init")
+        self._h = h
+
+    def push_rows(self, gamma, y):
+        k = int(y.numel())
+        _check(lib().rg_push_rows(self._h, _dev(gamma, self.tdtype, "gamma", k * self.m),
+                                  _dev(y, self.tdtype, "y", k), k), "rg_push_rows")
+
+    def solution(self, out=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty(self.m, dtype=self.tdtype, device="cuda")
+        _check(lib().rg_solution(self._h, _dev(out, self.tdtype, "x", self.m)), "rg_solution")
+        return out
+
+    def rank(self):
+        r = ctypes.c_int32()
+        _check(lib().rg_rank(self._h, ctypes.byref(r)), "rg_rank")
+        return r.value
+
+    def flags(self):
+        f = ctypes.c_uint32()
+        _check(lib().rg_status_flags(self._h, ctypes.byref(f)), "rg_status_flags")
+        return f.value
+
+    def reset(self):
+        _check(lib().rg_reset(self._h), "rg_reset")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(lib().rg_destroy(self._h), "rg_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def workspace_bytes(ms, r_max=None, dtype="f32"):
+    ms = np.ascontiguousarray(ms, dtype=np.int32)
+    rp = None if r_max is None else np.ascontiguousarray(r_max, dtype=np.int32)
+    code = RG_F64 if dtype in ("f64", np.float64) else RG_F32
+    return int(lib().rg_workspace_bytes(len(ms), ms.ctypes.data_as(_p),
+                                        None if rp is None else rp.ctypes.data_as(_p), code))

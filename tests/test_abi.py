@@ -1,0 +1,65 @@
+"""The C ABI library loads on a CPU host, exports every symbol include/rg.h
+declares, and rejects invalid arguments before touching a device."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_2106_11594_amd import rg
+
+
+@pytest.fixture(scope="module")
+def L():
+    return rg.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = rg.header_functions()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(rg._SIGS), "binding and header disagree"
+
+
+def test_status_strings(L):
+    for code, text in rg._STATUS.items():
+        assert L.rg_status_string(code).decode() == text
+
+
+def test_invalid_arguments_need_no_device(L):
+    h = ctypes.c_void_p()
+    assert L.rg_init(ctypes.byref(h), 0, None) == 1
+    assert L.rg_init(None, 4, None) == 1
+    ms = np.array([4, 0], dtype=np.int32)
+    assert L.rg_batch_init(ctypes.byref(h), 2, ms.ctypes.data_as(ctypes.c_void_p), None, None) == 1
+    ms = np.array([4, 5], dtype=np.int32)
+    rmax = np.array([5, 5], dtype=np.int32)  # r_max > m
+    assert L.rg_batch_init(ctypes.byref(h), 2, ms.ctypes.data_as(ctypes.c_void_p),
+                           rmax.ctypes.data_as(ctypes.c_void_p), None) == 1
+    assert L.rg_batch_init(ctypes.byref(h), 0, ms.ctypes.data_as(ctypes.c_void_p), None, None) == 1
+    for f in ("rg_push_rows",):
+        assert getattr(L, f)(None, None, None, 3) == 1
+    assert L.rg_solution(None, None) == 1
+    assert L.rg_reset(None) == 1
+    assert L.rg_destroy(None) == 1
+    r = ctypes.c_int32()
+    assert L.rg_rank(None, ctypes.byref(r)) == 1
+    assert L.rg_batch_push(None, None, None, None, None) == 1
+    assert L.rg_batch_adjoint(None, None, None, None, None, None, None, None) == 1
+
+
+def test_default_options(L):
+    o = rg.Options()
+    o.dtype, o.r_max, o.eps, o.flags = 7, 7, 7.0, 7
+    L.rg_default_options(ctypes.byref(o))
+    assert (o.dtype, o.r_max, o.eps, o.stream, o.flags) == (rg.RG_F32, 0, -1.0, None, 0)
+
+
+def test_workspace_bytes_layout():
+    """C, Ct (r_max x ldm) and P^-1 (r_max^2) per stream plus w, meta, order."""
+    b32 = rg.workspace_bytes([64], [16], "f32")
+    b64 = rg.workspace_bytes([64], [16], "f64")
+    state32 = (2 * 16 * 64 + 16 * 16) * 4
+    assert b32 >= state32 and b64 >= 2 * state32
+    assert rg.workspace_bytes([64], None) > rg.workspace_bytes([64], [16])
+    assert rg.workspace_bytes([0]) == 0

@@ -1,0 +1,226 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances:
+  FP64 streams: same decisions (rank and the accepted rows C, compared bit for
+    bit), x within 1e-11 relative.  Both sides run Algorithm 1 in IEEE double;
+    only summation order and the coordinate form x = Ct^T w differ, which moves
+    x by a few ulps times the condition of the basis (kappa(C) <= ~1e3 here).
+  FP32 streams: same decisions (rank and C bit for bit: C holds raw input rows,
+    exactly representable), x within 1e-5 relative when kappa(C) <= 1e3 and
+    within 0.1 * kappa(C) * 2^-23 above that.  First-order perturbation of the
+    FP32-stored Ct and P^-1 (relative error ~2^-24 per element) moves x by
+    O(kappa(C) * 2^-23); the constant 0.1 is three times the worst ratio seen
+    in an FP64 emulation of the FP32 arithmetic over batched-workload streams.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import ref_c
+from paper_2106_11594_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+EPS32 = 2.0 ** -23
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    ref_c.build()
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(np.asarray(a) - b) / (nb if nb > 0 else 1.0)
+
+
+def _f32_tol(C):
+    kap = np.linalg.cond(C) if C.shape[0] else 1.0
+    return (1e-5 if kap <= 1e3 else 0.1 * kap * EPS32), kap
+
+
+def _single(A, Y, dtype, eps=None, r_max=None, chunks=None, flags=0):
+    import torch
+    from paper_2106_11594_amd import rg
+    td = torch.float32 if dtype == "f32" else torch.float64
+    s = rg.Solver(A.shape[1], r_max=r_max, dtype=dtype, eps=eps, flags=flags)
+    At = torch.from_numpy(np.ascontiguousarray(A)).to("cuda", td)
+    Yt = torch.from_numpy(np.ascontiguousarray(Y)).to("cuda", td)
+    bounds = chunks or [0, A.shape[0]]
+    for a, b in zip(bounds[:-1], bounds[1:]):
+        s.push_rows(At[a:b].contiguous(), Yt[a:b].contiguous())
+    x = s.solution().double().cpu().numpy()
+    return x, s
+
+
+def _state(s_or_batch, b=0):
+    from paper_2106_11594_amd import rg
+    if isinstance(s_or_batch, rg.Solver):
+        h = rg.Batch.__new__(rg.Batch)
+        h._h, h.ms, h.B, h.tdtype = s_or_batch._h, np.array([s_or_batch.m], np.int32), 1, s_or_batch.tdtype
+        C, Ct, P, w = rg.Batch.get_state(h, b)
+        h._h = None
+        return [t.double().cpu().numpy() for t in (C, Ct, P, w)]
+    return [t.double().cpu().numpy() for t in s_or_batch.get_state(b)]
+
+
+@pytest.mark.parametrize("n", [700, 2000])
+def test_single_f64_vs_oracle(n):
+    s = W.single_f64(n=n)
+    x, h = _single(s.A, s.Y, "f64", eps=s.eps)
+    xo, ro, Co, Cto, Po = ref_c.solve(s.A, s.Y, eps=s.eps)
+    assert h.rank() == ro == 16 and h.flags() == 0
+    C, Ct, P, w = _state(h)
+    assert np.array_equal(C, Co)
+    assert _rel(x, xo) <= 1e-11
+    assert _rel(Ct, Cto) <= 1e-10 and _rel(P, Po) <= 1e-10
+
+
+def test_single_f64_default_eps():
+    s = W.single_f64(n=500, m=48, r=12, seed=3)
+    x, h = _single(s.A, s.Y, "f64")
+    xo, ro, *_ = ref_c.solve(s.A, s.Y, eps=-1.0)
+    assert h.rank() == ro == 12
+    assert _rel(x, xo) <= 1e-11
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_single_f32_vs_oracle(seed):
+    s = W.single_f64(n=1200, m=96, r=24, seed=seed)
+    A32 = s.A.astype(np.float32).astype(np.float64)
+    Y32 = s.Y.astype(np.float32).astype(np.float64)
+    x, h = _single(A32, Y32, "f32", eps=1e-3)
+    xo, ro, Co, *_ = ref_c.solve(A32, Y32, eps=1e-3)
+    assert h.rank() == ro == 24 and h.flags() == 0
+    C, *_ = _state(h)
+    assert np.array_equal(C, Co)
+    tol, kap = _f32_tol(Co)
+    assert _rel(x, xo) <= tol, (kap, _rel(x, xo))
+
+
+def test_worked_example_f64():
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "worked_example_m2.json")))
+    A = np.array(g["rows"], float)
+    Y = np.array(g["y"], float)
+    x, h = _single(A, Y, "f64", eps=1e-12)
+    assert h.rank() == 2
+    assert np.allclose(x, [20 / 11, 12 / 11], rtol=1e-14, atol=1e-15)
+    C, Ct, P, w = _state(h)
+    assert np.array_equal(C, [[1, 0], [1, 1]])
+    assert np.allclose(Ct, [[1, -1], [0, 1]], atol=1e-15)
+    assert np.allclose(P, np.array([[2, 1], [1, 6]]) / 11, atol=1e-15)
+    assert np.allclose(w, [20 / 11, 32 / 11], atol=1e-14)
+
+
+def test_min_norm_example():
+    x, h = _single(np.array([[1, 1, 0], [2, 2, 0]], float), np.array([2.0, 2.0]), "f64", eps=1e-12)
+    assert h.rank() == 1
+    assert np.allclose(x, [0.6, 0.6, 0.0], rtol=1e-15, atol=1e-16)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_edge_cases(dtype):
+    import torch
+    from paper_2106_11594_amd import rg
+    td = torch.float32 if dtype == "f32" else torch.float64
+    # k = 0 push and the empty state
+    s = rg.Solver(5, dtype=dtype)
+    s.push_rows(torch.empty((0, 5), device="cuda", dtype=td), torch.empty(0, device="cuda", dtype=td))
+    assert s.rank() == 0 and np.all(s.solution().cpu().numpy() == 0)
+    # zero rows are no-ops
+    x, h = _single(np.zeros((4, 5)), np.arange(4.0), dtype)
+    assert h.rank() == 0 and np.all(x == 0) and h.flags() == 0
+    # m = 1
+    x, h = _single(np.array([[2.0], [0.0], [-1.0]]), np.array([4.0, 3.0, 1.0]), dtype, eps=1e-6)
+    assert h.rank() == 1 and abs(x[0] - (8.0 - 1.0) / 5.0) < 1e-6
+    # single row closed form x = Gamma y / ||Gamma||^2
+    G = np.array([[3.0, -1.0, 2.0, 0.5]])
+    x, h = _single(G, np.array([7.0]), dtype)
+    assert h.rank() == 1 and np.allclose(x, G[0] * 7.0 / (G[0] @ G[0]), rtol=1e-6)
+    # full column rank: normal equations
+    rng = np.random.default_rng(4)
+    A = rng.integers(-4, 5, size=(40, 6)).astype(float)
+    Y = rng.integers(-9, 9, size=40).astype(float)
+    x, h = _single(A, Y, dtype, eps=1e-4 if dtype == "f32" else 1e-10)
+    assert h.rank() == 6
+    assert _rel(x, np.linalg.solve(A.T @ A, A.T @ Y)) <= (1e-5 if dtype == "f32" else 1e-12)
+    # exact duplicates only
+    x, h = _single(np.tile([[1.0, 2.0, 2.0]], (5, 1)), np.arange(5.0), dtype)
+    assert h.rank() == 1 and np.allclose(x, np.array([1, 2, 2]) * 2.0 / 9.0, rtol=1e-6)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_sticky_flags(dtype):
+    from paper_2106_11594_amd import rg
+    s = W.single_f64(n=60, m=16, r=6)
+    # rank capacity: r_max = 3 < rank 6
+    x, h = _single(s.A, s.Y, dtype, r_max=3)
+    assert h.rank() == 3 and h.flags() == rg.FLAG_RANK_CAPACITY
+    # a NaN row stops the stream; rows before it stay applied
+    A = s.A.copy()
+    A[30, 2] = np.nan
+    x, h = _single(A, s.Y, dtype)
+    assert h.flags() == rg.FLAG_NONFINITE
+    x2, h2 = _single(s.A[:30], s.Y[:30], dtype)
+    assert h.rank() == h2.rank() and np.array_equal(x, x2)
+    # reset clears the flag; the state is empty again
+    h.reset()
+    assert h.flags() == 0 and h.rank() == 0
+    Y = s.Y.copy()
+    Y[5] = np.inf
+    x, h = _single(s.A, Y, dtype)
+    assert h.flags() == rg.FLAG_NONFINITE
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_incremental_equals_one_push_and_deterministic(dtype):
+    s = W.single_f64(n=900, m=80, r=20, seed=9)
+    x1, h1 = _single(s.A, s.Y, dtype)
+    x2, h2 = _single(s.A, s.Y, dtype, chunks=[0, 1, 17, 300, 301, 900])
+    x3, h3 = _single(s.A, s.Y, dtype)
+    assert h1.rank() == h2.rank() == h3.rank() == 20
+    assert np.array_equal(x1, x2) and np.array_equal(x1, x3)
+
+
+def _batch_check(bt, dtype, eps, flags=0):
+    from tests.gpu_util import run_batch
+    xs, ranks, fl, h = run_batch(bt, dtype, eps=eps, flags=flags)
+    assert (fl == 0).all()
+    Xo, xoff, ro, st, _ = ref_c.solve_batch(bt.ms, bt.row_ptr, bt.a_off, bt.A, bt.Y, eps=eps, nthreads=8)
+    assert (st == 0).all()
+    worst = 0.0
+    for b in range(bt.B):
+        A, Y = bt.stream(b)
+        assert ranks[b] == ro[b] == min(int(bt.rs[b]), A.shape[0]), b
+        xo = Xo[xoff[b]:xoff[b] + bt.ms[b]]
+        if dtype == "f64":
+            assert _rel(xs[b], xo) <= 1e-11, b
+        else:
+            _, _, Co, *_ = ref_c.solve(A, Y, eps=eps)
+            C, *_ = _state(h, b)
+            assert np.array_equal(C, Co), b
+            tol, kap = _f32_tol(Co)
+            assert _rel(xs[b], xo) <= tol, (b, kap, _rel(xs[b], xo))
+        worst = max(worst, _rel(xs[b], xo))
+    return worst
+
+
+def test_batched_f32_vs_oracle():
+    bt = W.batched(B=48, n_scale=0.3, dtype="f32")
+    _batch_check(bt, "f32", 1e-3)
+
+
+def test_batched_f64_vs_oracle():
+    bt = W.batched(B=32, m_hi=160, n_scale=0.3, dtype="f64")
+    _batch_check(bt, "f64", 1e-8)
+
+
+def test_batched_generic_kernel_matches():
+    from paper_2106_11594_amd import rg
+    bt = W.batched(B=24, n_scale=0.25, dtype="f32", seed=1)
+    _batch_check(bt, "f32", 1e-3, flags=rg.OPT_GENERIC_KERNEL)
