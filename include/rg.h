@@ -63,6 +63,8 @@ typedef enum { RG_F32 = 0, RG_F64 = 1 } rg_dtype;
 /* Option bits. */
 #define RG_OPT_NO_REPROJECT   0x1u  /* skip the second projection pass of independent rows */
 #define RG_OPT_GENERIC_KERNEL 0x2u  /* force the global-memory kernel (testing) */
+#define RG_OPT_SERIAL_CLASSES 0x4u  /* launch the size classes one after another on the
+                                       handle's stream instead of on forked streams */
 
 typedef struct {
     int32_t dtype;   /* rg_dtype */

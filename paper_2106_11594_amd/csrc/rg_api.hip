@@ -33,7 +33,9 @@ struct rg_ctx {
     std::vector<StreamMeta> h_meta;
     std::vector<int64_t> cost;
     // per-family segments of d_order
-    std::vector<int> fam_begin, fam_count;
+    std::vector<int> fam_begin, fam_count, fam_rows;
+    hipStream_t aux[RG_MAX_FAMILIES] = {};
+    hipEvent_t fork = nullptr, join[RG_MAX_FAMILIES] = {};
     int m_max_generic = 0, rmax_max_generic = 0;
     int m_max_all = 0, rmax_max_all = 0;
 };
@@ -101,6 +103,11 @@ rg_status upload_order(rg_ctx *h) {
     order.reserve(B);
     h->fam_begin.assign(nfam, 0);
     h->fam_count.assign(nfam, 0);
+    h->fam_rows.assign(nfam, 0);
+    for (int b = 0; b < B; ++b) {
+        const int f = h->h_meta[b].cls + 1;
+        h->fam_rows[f] = std::max(h->fam_rows[f], (int)h->h_meta[b].r_max);
+    }
     for (int f = 0; f < nfam; ++f) {
         std::stable_sort(fam[f].begin(), fam[f].end(),
                          [&](int32_t a, int32_t c) { return h->cost[a] > h->cost[c]; });
@@ -110,6 +117,9 @@ rg_status upload_order(rg_ctx *h) {
     }
     HIPCHK(hipMemcpyAsync(h->d_order, order.data(), sizeof(int32_t) * B, hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
+    if (h->dtype == RG_F32)
+        for (int f = 1; f < nfam; ++f)
+            if (h->fam_count[f] > 0) HIPCHK(rg::prepare_class(f - 1, h->fam_rows[f]));
     return RG_OK;
 }
 
@@ -129,14 +139,28 @@ rg_status push_impl(rg_ctx *h, const void *gamma, const void *y, const int64_t *
     a.eps = h->eps;
     a.opts = h->opts;
     HIPCHK(rg::launch_reset_counter(h->d_counter, h->stream));
-    // size-class families (register-resident kernels)
-    for (int f = 1; f < RG_MAX_FAMILIES; ++f) {
+    // Size-class families run concurrently on forked streams (largest class
+    // first), joined back into the handle's stream.
+    const bool serial = (h->opts & RG_OPT_SERIAL_CLASSES) != 0;
+    int nact = 0;
+    for (int f = 1; f < RG_MAX_FAMILIES; ++f) nact += h->fam_count[f] > 0;
+    if (nact > 0 && !serial) HIPCHK(hipEventRecord(h->fork, h->stream));
+    for (int f = RG_MAX_FAMILIES - 1; f >= 1; --f) {
         if (h->fam_count[f] == 0) continue;
         a.order = h->d_order + h->fam_begin[f];
         a.n_order = h->fam_count[f];
         a.counter = h->d_counter + f;
-        HIPCHK(rg::launch_push_class<T>(f - 1, a, h->num_cus, h->stream));
+        if (serial) {
+            HIPCHK(rg::launch_push_class<T>(f - 1, a, h->fam_rows[f], h->stream));
+            continue;
+        }
+        HIPCHK(hipStreamWaitEvent(h->aux[f], h->fork, 0));
+        HIPCHK(rg::launch_push_class<T>(f - 1, a, h->fam_rows[f], h->aux[f]));
+        HIPCHK(hipEventRecord(h->join[f], h->aux[f]));
     }
+    if (!serial)
+        for (int f = 1; f < RG_MAX_FAMILIES; ++f)
+            if (h->fam_count[f] > 0) HIPCHK(hipStreamWaitEvent(h->stream, h->join[f], 0));
     if (h->fam_count[0] > 0) {
         a.order = h->d_order + h->fam_begin[0];
         a.n_order = h->fam_count[0];
@@ -150,6 +174,17 @@ rg_status push_impl(rg_ctx *h, const void *gamma, const void *y, const int64_t *
 }
 
 bool valid_handle(rg_handle h) { return h != nullptr && h->ws != nullptr; }
+
+void release_streams(rg_ctx *h) {
+    for (int f = 0; f < RG_MAX_FAMILIES; ++f) {
+        if (h->aux[f]) (void)hipStreamDestroy(h->aux[f]);
+        if (h->join[f]) (void)hipEventDestroy(h->join[f]);
+        h->aux[f] = nullptr;
+        h->join[f] = nullptr;
+    }
+    if (h->fork) (void)hipEventDestroy(h->fork);
+    h->fork = nullptr;
+}
 
 }  // namespace
 
@@ -250,11 +285,19 @@ rg_status rg_batch_init(rg_handle *out, int32_t B, const int32_t *m, const int32
         hipMemcpyAsync(h->d_meta, h->h_meta.data(), sizeof(StreamMeta) * B, hipMemcpyHostToDevice, h->stream) !=
             hipSuccess)
         st = RG_E_DEVICE;
+    if (st == RG_OK) {
+        if (hipEventCreateWithFlags(&h->fork, hipEventDisableTiming) != hipSuccess) st = RG_E_DEVICE;
+        for (int f = 1; f < RG_MAX_FAMILIES && st == RG_OK; ++f)
+            if (hipStreamCreateWithFlags(&h->aux[f], hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&h->join[f], hipEventDisableTiming) != hipSuccess)
+                st = RG_E_DEVICE;
+    }
     h->cost.resize(B);
     for (int b = 0; b < B; ++b) h->cost[b] = (int64_t)h->h_meta[b].m * h->h_meta[b].m * h->h_meta[b].r_max;
     if (st == RG_OK) st = upload_order(h);
     if (st != RG_OK) {
         (void)hipFree(h->ws);
+        release_streams(h);
         delete h;
         return st;
     }
@@ -399,6 +442,7 @@ rg_status rg_destroy(rg_handle h) {
         if (hipStreamSynchronize(h->stream) != hipSuccess) st = RG_E_DEVICE;
         if (hipFree(h->ws) != hipSuccess) st = RG_E_DEVICE;
     }
+    release_streams(h);
     delete h;
     return st;
 }

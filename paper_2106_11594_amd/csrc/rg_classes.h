@@ -1,14 +1,20 @@
-// Size classes of the register-resident batched kernel and their launcher.
+// Size classes of the on-chip batched kernel (rg_rk.hip) and their launcher.
 #pragma once
 #include "rg_internal.h"
 
-#define RG_NUM_CLASSES 0
+#define RG_NUM_CLASSES 8
 #define RG_MAX_FAMILIES (1 + RG_NUM_CLASSES)  // family 0 = generic global-state kernel
 
 namespace rg {
 // Class index for a stream of m regressors and capacity r_max, or -1 when the
-// stream goes to the generic kernel.
+// stream goes to the generic kernel (FP64 state, or too large for the chip).
 int choose_class(int m, int r_max, int dtype);
+int class_rmax(int cls);
+// Raise the dynamic-LDS limit of class cls's kernel to what rows_alloc needs
+// (once per handle, at init).
+hipError_t prepare_class(int cls, int rows_alloc);
+// One launch over a.n_order streams of class cls; rows_alloc = the largest
+// r_max among them (rows of Ct reserved in LDS).
 template <typename T>
-hipError_t launch_push_class(int cls, const PushArgs<T> &a, int num_cus, hipStream_t s);
+hipError_t launch_push_class(int cls, const PushArgs<T> &a, int rows_alloc, hipStream_t s);
 }  // namespace rg

@@ -17,7 +17,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "rg.h")
 
 RG_F32, RG_F64 = 0, 1
 FLAG_NONFINITE, FLAG_RANK_CAPACITY, FLAG_DENOMINATOR = 0x1, 0x2, 0x4
-OPT_NO_REPROJECT, OPT_GENERIC_KERNEL = 0x1, 0x2
+OPT_NO_REPROJECT, OPT_GENERIC_KERNEL, OPT_SERIAL_CLASSES = 0x1, 0x2, 0x4
 _STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "HIP runtime error", 4: "unsupported size"}
 
 
@@ -279,3 +279,52 @@ def workspace_bytes(ms, r_max=None, dtype="f32"):
     code = RG_F64 if dtype in ("f64", np.float64) else RG_F32
     return int(lib().rg_workspace_bytes(len(ms), ms.ctypes.data_as(_p),
                                         None if rp is None else rp.ctypes.data_as(_p), code))
+
+
+def _autograd_function():
+    import torch
+
+    class RGSolve(torch.autograd.Function):
+        """x_b = A_b^+ Y_b for equal-shape problems, by rank-Greville on the GPU.
+
+        forward: A (B, n, m), Y (B, n) -> x (B, m); every row of problem b is
+        pushed through Algorithm 1 in order (rg_batch_push), then
+        x_b = Ct_b^T w_b (rg_batch_solution).
+        backward: the adjoint kernel (rg_batch_adjoint) gives dL/dA and dL/dY
+        at constant rank from the maintained factorisation.
+        """
+
+        @staticmethod
+        def forward(ctx, A, Y, eps, r_max):
+            B, n, m = A.shape
+            A = A.contiguous()
+            Y = Y.contiguous()
+            h = Batch(np.full(B, m, np.int32), r_max=None if r_max is None else np.full(B, r_max, np.int32),
+                      dtype=A.dtype, eps=eps)
+            row_ptr = torch.arange(0, (B + 1) * n, n, dtype=torch.int64, device=A.device)
+            a_off = torch.arange(0, B * n * m, n * m, dtype=torch.int64, device=A.device)
+            h.plan(np.full(B, n, np.int64))
+            h.push(A.view(-1), Y.view(-1), row_ptr, a_off)
+            x = h.solution().view(B, m)
+            ctx.h = h
+            ctx.save_for_backward(A, Y, row_ptr, a_off)
+            return x
+
+        @staticmethod
+        def backward(ctx, gx):
+            A, Y, row_ptr, a_off = ctx.saved_tensors
+            dA, dY = ctx.h.adjoint(A.view(-1), Y.view(-1), row_ptr, a_off, gx.contiguous().view(-1))
+            return dA.view_as(A), dY.view_as(Y), None, None
+
+    return RGSolve
+
+
+_RGSolve = None
+
+
+def rg_solve(A, Y, eps=None, r_max=None):
+    """Differentiable batched minimum-norm least squares (see RGSolve)."""
+    global _RGSolve
+    if _RGSolve is None:
+        _RGSolve = _autograd_function()
+    return _RGSolve.apply(A, Y, eps, r_max)

@@ -224,3 +224,33 @@ def test_batched_generic_kernel_matches():
     from paper_2106_11594_amd import rg
     bt = W.batched(B=24, n_scale=0.25, dtype="f32", seed=1)
     _batch_check(bt, "f32", 1e-3, flags=rg.OPT_GENERIC_KERNEL)
+
+
+def test_batched_largest_classes():
+    """Shapes at the top of the on-chip kernel's range (m = 256 with ranks up
+    to 128 and capacities up to 132), checked against the oracle."""
+    from paper_2106_11594_amd import rg
+    from tests.gpu_util import to_device
+    shapes = [(256, 128, 300, 132), (256, 120, 260, 128), (200, 96, 240, 100), (64, 30, 90, 34)]
+    streams = []
+    for idx, (m, r, n, _) in enumerate(shapes):
+        rng = np.random.default_rng(100 + idx)
+        A = W.lowrank_rows(rng, m, r, n)
+        Y, _ = W.targets(rng, A)
+        streams.append((A, Y.astype(np.float32).astype(np.float64)))
+    ms, ns, row_ptr, a_off, A, Y = W.pack(streams, 1e-3, "f32")
+    bt = W.Batch(ms, np.array([s[1] for s in shapes], np.int32), ns, row_ptr, a_off, A, Y, 1e-3, "f32")
+    caps = np.array([s[3] for s in shapes], np.int32)
+    Ad, Yd, rp, ao = to_device(bt, "f32")
+    h = rg.Batch(bt.ms, r_max=caps, dtype="f32", eps=1e-3)
+    h.push(Ad, Yd, rp, ao)
+    x = h.solution().double().cpu().numpy()
+    ranks, fl = h.rank(), h.flags()
+    for b, (m, r, n, cap) in enumerate(shapes):
+        Ab, Yb = bt.stream(b)
+        xo, ro, Co, *_ = ref_c.solve(Ab, Yb, eps=1e-3, cap=cap)
+        assert fl[b] == 0 and ranks[b] == ro == r
+        C, *_ = _state(h, b)
+        assert np.array_equal(C, Co)
+        tol, kap = _f32_tol(Co)
+        assert _rel(x[h.x_off[b]:h.x_off[b] + m], xo) <= tol, (b, kap)
