@@ -266,7 +266,6 @@ __global__ void __launch_bounds__(K::NT) k_push_rk(PushArgs<float> a, int rows_a
 
     const bool reproject = !(a.opts & OPT_NO_REPROJECT);
     int rba = (r + PK - 1) / PK;
-    int iaa = (r + 15) / 16;
     int cur = 0;  // ring slot of row i
     int64_t applied = 0;
     float y_next = a.y[i0];
@@ -493,7 +492,6 @@ __global__ void __launch_bounds__(K::NT) k_push_rk(PushArgs<float> a, int rows_a
             }
             r += 1;
             rba = (r + PK - 1) / PK;
-            iaa = (r + 15) / 16;
             __syncthreads();
         }
         ++applied;
