@@ -65,6 +65,9 @@ typedef enum { RG_F32 = 0, RG_F64 = 1 } rg_dtype;
 #define RG_OPT_GENERIC_KERNEL 0x2u  /* force the global-memory kernel (testing) */
 #define RG_OPT_SERIAL_CLASSES 0x4u  /* launch the size classes one after another on the
                                        handle's stream instead of on forked streams */
+#define RG_OPT_ROW_BY_ROW     0x8u  /* never apply dependent rows in blocks: every row is
+                                       one call of Algorithm 1 (reference path for the
+                                       blocked variant) */
 
 typedef struct {
     int32_t dtype;   /* rg_dtype */

@@ -1,8 +1,9 @@
-// Size classes of the on-chip batched kernel (rg_rk.hip) and their launcher.
+// Size classes of the on-chip batched kernels (rg_rk.hip: row by row, small
+// streams; rg_mf.hip: blocked, larger streams) and their launcher.
 #pragma once
 #include "rg_internal.h"
 
-#define RG_NUM_CLASSES 8
+#define RG_NUM_CLASSES 9
 #define RG_MAX_FAMILIES (1 + RG_NUM_CLASSES)  // family 0 = generic global-state kernel
 
 namespace rg {
@@ -17,4 +18,9 @@ hipError_t prepare_class(int cls, int rows_alloc);
 // r_max among them (rows of Ct reserved in LDS).
 template <typename T>
 hipError_t launch_push_class(int cls, const PushArgs<T> &a, int rows_alloc, hipStream_t s);
+// The blocked kernel's variants (rg_mf.hip), numbered 0..5.
+int mf_choose(int m, int r_max);
+int mf_rmax(int v);
+hipError_t mf_prepare(int v, int r_max);
+hipError_t mf_launch(int v, const PushArgs<float> &a, int r_max, hipStream_t s);
 }  // namespace rg

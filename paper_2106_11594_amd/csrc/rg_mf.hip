@@ -1,0 +1,911 @@
+// Batched rank-Greville update with FP32 state on chip and blocks of dependent
+// rows applied through FP64 matrix-core products (v_mfma_f64_16x16x4f64).
+//
+// One workgroup of NW waves (4 or 8) owns one stream for a whole push.  Lane
+// l of wave w has i = l & 15 and g = l >> 4.  Residency:
+//   Ct    LDS, FP32, row-major, leading dimension MMAX.  Logical float4 chunk
+//         c of row k sits at physical chunk c ^ (k & 15), so that the 16 rows
+//         a matrix-core operand touches fall into different banks;
+//   C     registers, FP32: c[s][tau] = C[4s + g][16 (w + NW tau) + i]
+//         (the A operand of C^T for column tile w + NW tau, K-step s);
+//   P^-1  registers, FP64, 16 x 16 output tiles (u', u) for the column tiles
+//         u = w + NW ups of this wave: p[u'][ups][v] = P^-1[16u' + 4v + g][16u + i];
+//   w     registers, FP64: wr[ups][v] = w[16 (w + NW ups) + 4v + g].
+// The matrix-core operands of v_mfma_f64_16x16x4f64 are A[i][g] and B[g][i]
+// on lane (i, g), and the result D[4v + g][i] sits in register v of lane
+// (i, g); the layouts above are chosen so that results feed later products
+// without shuffles.
+//
+// Rows are taken in two modes.
+//  Row mode (Algorithm 1, one row): gamma = Ct Gamma over LDS with 16-lane
+//   DPP sums; C^T gamma, zeta = P^-1 gamma and gamma^T w per column tile with
+//   the register-resident C and P^-1 and one reduce-scatter over the 4 lane
+//   groups; rank test on workgroup sums; then the dependent update of P^-1
+//   and w (Theorems 5 and 6), or the independent one (second projection pass,
+//   Ct <- [Ct - gamma K^T; K^T], appends to C, P^-1 and w; Theorems 4 and 6).
+//  Block mode (up to 16 rows): G = Gamma_blk Ct^T and the rejections
+//   R = Gamma_blk - G C on the matrix cores; the rank test of Section 3 on
+//   every row; the longest prefix of dependent rows is applied at once.
+//   Applying the dependent rows j = 0..nd-1 one after another is the same as
+//   the Woodbury form with Z = P^-1 G^T, S = I + G Z:
+//     P^-1 <- P^-1 - Z S^-1 Z^T,   w <- w + Z S^-1 (y - G w),
+//   and the pivots of the Cholesky factor S = L L^T are exactly the
+//   sequential Greville denominators 1 + gamma_j^T P_j^-1 gamma_j, so their
+//   test is the same.  With T = Z L^-T the updates are P^-1 -= T T^T and
+//   w += T (L^-1 (y - G w)).  The first row that is not dependent is then taken
+//   in row mode.
+// The kernel enters block mode after a dependent row and leaves it at an
+// independent one; every branch is on workgroup-uniform values.
+#include "rg_classes.h"
+#include "rg_lanes.h"
+
+namespace rg {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ inline d4 mma(double a, double b, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+
+// FP64 value of a register-resident FP32 state element.  The empty asm keeps
+// the compiler from hoisting the conversion out of the row loop, which would
+// keep an FP64 copy of all of C live and double its register footprint.
+__device__ inline double f64_of(float v) {
+    asm volatile("" : "+v"(v));
+    return (double)v;
+}
+
+template <int RMAX_, int MMAX_, int NW_>
+struct MF {
+    static constexpr int RMAX = RMAX_, MMAX = MMAX_, NW = NW_;
+    static_assert((RMAX == 64 || RMAX == 128) && (RMAX / 16) % NW == 0, "whole row tiles per wave");
+    static_assert(MMAX % 64 == 0 && MMAX <= 256 && (NW == 4 || NW == 8), "4 or 8 waves");
+    static constexpr int NT = 64 * NW;
+    static constexpr int NU = RMAX / 16, UPW = NU / NW;               // 16-row tiles, per wave
+    static constexpr int NTT = MMAX / 16, TPW = (NTT + NW - 1) / NW;  // 16-column tiles, per wave
+    static_assert(TPW <= 4 && UPW <= 2, "one reduce-scatter holds the column and zeta totals");
+    static constexpr int RS = 4 * NW;                                 // row stride of a thread in row mode
+    static constexpr int NB = RMAX / RS;                              // Ct rows per thread in row mode
+    static constexpr int KB = 16;                                     // rows per block
+    static constexpr int CH = MMAX / 4;                               // float4 chunks per row
+    // X1 (doubles): block-mode scalars and partial sums, or the row-mode vectors
+    static constexpr int X1_RR = 0, X1_GW = 16 * NW, X1_GG = 32 * NW, X1_YV = 32 * NW + 16;
+    static constexpr int X1_SP = 32 * NW + 64, X1_L = X1_SP + 1024, X1_C = X1_L + 256, X1_COL = X1_C + 32;
+    static constexpr int X1_DW = X1_COL + 32;
+    static constexpr int X1_GAM = 0, X1_ZETA = RMAX, X1_RED = 2 * RMAX, X1_GR = 2 * RMAX + 4 * NW;
+    static constexpr int X1_D = cmax(cmax(KB * MMAX / 2, X1_DW + RMAX), X1_GR + MMAX);
+    // X2 (doubles): G (16 x RMAX), then Z and T (RMAX x 16); or the row ring
+    static constexpr int X2_D = cmax(KB * RMAX, 3 * MMAX / 2);
+};
+
+// Swizzled positions of G[j][kk] (16 x RMAX) and of Z, T [kk][j] (RMAX x 16).
+template <int RMAX>
+__device__ inline int gpos(int j, int kk) { return j * RMAX + (kk ^ (4 * (j & 7))); }
+__device__ inline int zpos(int kk, int j) { return kk * 16 + (j ^ (4 * ((kk >> 1) & 3))); }
+
+// Sums of four per-lane partials over the workgroup (every thread gets them).
+template <int NW>
+__device__ inline void block_sum4(double &a, double &b, double &c, double &d, double *sred) {
+    a = sum64(a);
+    b = sum64(b);
+    c = sum64(c);
+    d = sum64(d);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        sred[4 * wid] = a;
+        sred[4 * wid + 1] = b;
+        sred[4 * wid + 2] = c;
+        sred[4 * wid + 3] = d;
+    }
+    __syncthreads();
+    a = b = c = d = 0.0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+        a += sred[4 * q];
+        b += sred[4 * q + 1];
+        c += sred[4 * q + 2];
+        d += sred[4 * q + 3];
+    }
+}
+
+template <class K>
+__global__ void __launch_bounds__(K::NT) k_push_mf(PushArgs<float> a, int ra) {
+    constexpr int RMAX = K::RMAX, MMAX = K::MMAX, NU = K::NU, UPW = K::UPW, TPW = K::TPW;
+    constexpr int NB = K::NB, KB = K::KB, CH = K::CH, NW = K::NW, NTT = K::NTT, RS = K::RS;
+    extern __shared__ double smem[];
+    float *sct = reinterpret_cast<float *>(smem);  // ra x MMAX (ra: multiple of 16)
+    double *x1 = smem + (size_t)ra * MMAX / 2;
+    double *x2 = x1 + K::X1_D;
+    float *x1f = reinterpret_cast<float *>(x1);   // block rows, 16 x MMAX, swizzled like Ct
+    float *ring = reinterpret_cast<float *>(x2);  // row mode: 3 rows of MMAX
+
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int b_id = a.order[blockIdx.x];
+    StreamMeta *M = a.meta + b_id;
+    const int m = M->m, rmax = M->r_max, ldm = M->ldm;
+    int r = M->r;
+    uint32_t flags = M->flags;
+    float *Cg = a.state + M->state_off;
+    float *Ctg = Cg + (size_t)rmax * ldm;
+    double *Pg = a.preg + M->p_off;
+    double *wg = a.wreg + M->w_off;
+    int64_t i0, i1, goff;
+    if (a.row_ptr) {
+        i0 = a.row_ptr[b_id];
+        i1 = a.row_ptr[b_id + 1];
+        goff = a.gamma_off[b_id];
+    } else {
+        i0 = 0;
+        i1 = a.k_single;
+        goff = 0;
+    }
+    if (flags != 0u || i0 >= i1) return;  // whole workgroup: nothing to do
+    const float *G0 = a.gamma + goff;     // row i starts at G0 + (i - i0) * m
+    const int cba4 = (m + 63) / 64;       // 64-column groups (row mode)
+    const int nq = (m + 15) / 16;         // 16-column chunks (block mode)
+
+    // ---- load the state ------------------------------------------------------
+    for (int idx = t; idx < ra * CH; idx += K::NT) {
+        const int k = idx / CH, c = idx - k * CH;
+        float v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int j = 4 * c + e;
+            v[e] = (k < r && j < m) ? Ctg[(size_t)k * ldm + j] : 0.0f;
+        }
+        *reinterpret_cast<float4 *>(sct + (size_t)k * MMAX + 4 * (c ^ (k & 15))) = make_float4(v[0], v[1], v[2], v[3]);
+    }
+    const int li = lane & 15, lg = lane >> 4;
+    float c[4 * NU][TPW];
+#pragma unroll
+    for (int s = 0; s < 4 * NU; ++s)
+#pragma unroll
+        for (int tau = 0; tau < TPW; ++tau) {
+            const int row = 4 * s + lg, col = 16 * (wv + NW * tau) + li;
+            c[s][tau] = (row < r && col < m) ? Cg[(size_t)row * ldm + col] : 0.0f;
+        }
+    d4 p[NU][UPW];
+    double wr[UPW][4];
+#pragma unroll
+    for (int ups = 0; ups < UPW; ++ups) {
+        const int col = 16 * (wv + NW * ups) + li;
+#pragma unroll
+        for (int u2 = 0; u2 < NU; ++u2)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = 16 * u2 + 4 * v + lg;
+                p[u2][ups][v] = (row < r && col < r) ? Pg[(size_t)row * rmax + col] : 0.0;
+            }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int kk = 16 * (wv + NW * ups) + 4 * v + lg;
+            wr[ups][v] = kk < r ? wg[kk] : 0.0;
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+
+    const bool reproject = !(a.opts & OPT_NO_REPROJECT);
+    const bool use_blocks = !(a.opts & OPT_ROW_BY_ROW);
+    int64_t i = i0, applied = 0;
+    bool block_mode = false;
+    bool ring_ok = false;  // row mode: row i is in ring slot cur, pre holds row i + 1
+    int cur = 0;
+    constexpr int PF = (MMAX + K::NT - 1) / K::NT;
+    float pre[PF];
+    float y_next = 0.0f;
+
+    while (i < i1) {
+        // Lane indices are re-derived from an opaque copy of the lane id in every
+        // iteration, so the per-lane (swizzled) LDS addresses are computed where
+        // they are used instead of being held in registers across the loop.
+        int lane_l = lane;
+        asm volatile("" : "+v"(lane_l));
+        const int li = lane_l & 15, lg = lane_l >> 4, tl = 64 * wv + lane_l;
+        const int pk = tl >> 4, pj = tl & 15, pk15 = pk & 15;
+        if (block_mode) {
+            // ================= block of up to KB rows =================
+            __syncthreads();  // earlier readers of X1 / X2 are done
+            const int nblk = (int)min((int64_t)KB, i1 - i);
+            for (int idx = tl; idx < KB * CH; idx += K::NT) {
+                const int j = idx / CH, cc = idx - j * CH;
+                float v[4];
+                const float *src = G0 + (i - i0 + j) * (int64_t)m;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int col = 4 * cc + e;
+                    v[e] = (j < nblk && col < m) ? src[col] : 0.0f;
+                }
+                *reinterpret_cast<float4 *>(x1f + j * MMAX + 4 * (cc ^ j)) = make_float4(v[0], v[1], v[2], v[3]);
+            }
+            const double yrow = li < nblk ? (double)a.y[i + li] : 0.0;
+            __syncthreads();
+
+            // ---- G = Gamma_blk Ct^T: tiles u = wv + 4 ups of G^T ----
+            const int nur = (r + 15) / 16;
+            d4 gacc[UPW];
+#pragma unroll
+            for (int ups = 0; ups < UPW; ++ups) gacc[ups] = (d4){0.0, 0.0, 0.0, 0.0};
+            double gsq = 0.0;
+            {
+                // chunk 4q + g of a row with (row & 15) == i sits at physical chunk (4q + g) ^ i;
+                // the operands of chunk q + 1 are loaded while chunk q is multiplied
+                const float *gbase = x1f + li * MMAX;
+                const float *cbase[UPW];
+#pragma unroll
+                for (int ups = 0; ups < UPW; ++ups) cbase[ups] = sct + (size_t)(16 * (wv + NW * ups) + li) * MMAX;
+                float4 gb = *reinterpret_cast<const float4 *>(gbase + 4 * (lg ^ li));
+                float4 ca[UPW];
+#pragma unroll
+                for (int ups = 0; ups < UPW; ++ups)
+                    ca[ups] = wv + NW * ups < nur ? *reinterpret_cast<const float4 *>(cbase[ups] + 4 * (lg ^ li))
+                                                  : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll 1
+                for (int q = 0; q < nq; ++q) {
+                    const float4 gq = gb;
+                    float4 cq[UPW];
+#pragma unroll
+                    for (int ups = 0; ups < UPW; ++ups) cq[ups] = ca[ups];
+                    if (q + 1 < nq) {
+                        const int phn = (4 * q + 4 + lg) ^ li;
+                        gb = *reinterpret_cast<const float4 *>(gbase + 4 * phn);
+#pragma unroll
+                        for (int ups = 0; ups < UPW; ++ups)
+                            if (wv + NW * ups < nur) ca[ups] = *reinterpret_cast<const float4 *>(cbase[ups] + 4 * phn);
+                    }
+                    const double b0 = gq.x, b1 = gq.y, b2 = gq.z, b3 = gq.w;
+                    gsq += b0 * b0 + b1 * b1 + b2 * b2 + b3 * b3;
+#pragma unroll
+                    for (int ups = 0; ups < UPW; ++ups) {
+                        if (wv + NW * ups < nur) {
+                            gacc[ups] = mma((double)cq[ups].x, b0, gacc[ups]);
+                            gacc[ups] = mma((double)cq[ups].y, b1, gacc[ups]);
+                            gacc[ups] = mma((double)cq[ups].z, b2, gacc[ups]);
+                            gacc[ups] = mma((double)cq[ups].w, b3, gacc[ups]);
+                        }
+                    }
+                }
+            }
+            gsq = sum_rows(gsq);  // ||Gamma_i||^2
+            double gwp = 0.0;     // this wave's part of (G w)_i
+#pragma unroll
+            for (int ups = 0; ups < UPW; ++ups) {
+                const int u = wv + NW * ups;
+                if (u < nur) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        gwp += gacc[ups][v] * wr[ups][v];
+                        x2[gpos<RMAX>(li, 16 * u + 4 * v + lg)] = gacc[ups][v];
+                    }
+                }
+            }
+            gwp = sum_rows(gwp);
+            double gi[TPW][4];  // Gamma_blk[i][16 tl + 4 v + g] for this wave's column tiles
+#pragma unroll
+            for (int tau = 0; tau < TPW; ++tau)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    gi[tau][v] = wv + NW * tau < NTT ? (double)x1f[li * MMAX + 4 * ((4 * (wv + NW * tau) + v) ^ li) + lg] : 0.0;
+            __syncthreads();
+
+            // ---- R^T = Gamma_blk^T - C^T G^T and ||R_i||^2 ----
+            double rsq = 0.0;
+#pragma unroll
+            for (int tau = 0; tau < TPW; ++tau) {
+                if (wv + NW * tau < nq) {
+                    d4 d = (d4){gi[tau][0], gi[tau][1], gi[tau][2], gi[tau][3]};
+#pragma unroll
+                    for (int u2 = 0; u2 < NU; ++u2) {
+                        if (u2 < nur) {
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) {
+                                const int s = 4 * u2 + v;
+                                d = mma(f64_of(c[s][tau]), -x2[gpos<RMAX>(li, 4 * s + lg)], d);
+                            }
+                        }
+                    }
+                    rsq += d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + d[3] * d[3];
+                }
+            }
+            rsq = sum_rows(rsq);
+            if (lg == 0) {
+                x1[K::X1_RR + 16 * wv + li] = rsq;
+                x1[K::X1_GW + 16 * wv + li] = gwp;
+                if (wv == 0) {
+                    x1[K::X1_GG + li] = gsq;
+                    x1[K::X1_YV + li] = yrow;
+                }
+            }
+            __syncthreads();
+
+            // ---- rank test of every row; nd = longest dependent prefix ----
+            // every lane tests row i; the first failing row over lanes 0..15 ends the block
+            const double eps = a.eps >= 0.0 ? a.eps : ((double)m * m * r + (double)m * r + (double)m) * 0x1p-52;
+            int nd;
+            uint32_t stop = 0u;
+            {
+                double r2 = 0.0;
+#pragma unroll
+                for (int q = 0; q < NW; ++q) r2 += x1[K::X1_RR + 16 * q + li];
+                const double g2 = x1[K::X1_GG + li], yj = x1[K::X1_YV + li];
+                const bool bad = li < nblk && (!isfinite(g2) || !isfinite(yj));
+                const double nr = sqrt(r2);
+                const bool indep = li < nblk && !((r2 == 0.0) || (nr < eps) || (nr < eps * sqrt(g2)));
+                const uint64_t fail = __ballot(bad || indep) & 0xFFFFull;
+                const uint64_t nonf = __ballot(bad) & 0xFFFFull;
+                nd = fail ? (int)__builtin_ctzll(fail) : nblk;
+                if (fail && ((nonf >> nd) & 1ull)) stop = FLAG_NONFINITE;
+            }
+            double gwi = 0.0;
+#pragma unroll
+            for (int q = 0; q < NW; ++q) gwi += x1[K::X1_GW + 16 * q + li];
+            const double dyi = yrow - gwi;
+            if (nd == 0) {
+                if (stop) {
+                    flags |= stop;
+                    break;
+                }
+                block_mode = false;
+                ring_ok = false;
+                continue;
+            }
+
+            // ---- Z = P^-1 G^T and this wave's part of S = I + G Z ----
+            const bool rowok = li < nd;
+            d4 z[UPW];
+            d4 sacc = (d4){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int ups = 0; ups < UPW; ++ups) {
+                const int u = wv + NW * ups;
+                z[ups] = (d4){0.0, 0.0, 0.0, 0.0};
+                if (u < nur) {
+#pragma unroll
+                    for (int u2 = 0; u2 < NU; ++u2) {
+                        if (u2 < nur) {
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) {
+                                const double gb = rowok ? x2[gpos<RMAX>(li, 16 * u2 + 4 * v + lg)] : 0.0;
+                                z[ups] = mma(p[u2][ups][v], gb, z[ups]);
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const double ga = rowok ? x2[gpos<RMAX>(li, 16 * u + 4 * v + lg)] : 0.0;
+                        sacc = mma(ga, z[ups][v], sacc);
+                    }
+                }
+            }
+            // four records of partial sums of S; with 8 waves the upper half folds in first
+            if (NW == 8) {
+                if (wv >= 4) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) x1[K::X1_SP + 256 * (wv - 4) + 16 * (4 * v + lg) + li] = sacc[v];
+                }
+                __syncthreads();
+                if (wv < 4) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) sacc[v] += x1[K::X1_SP + 256 * wv + 16 * (4 * v + lg) + li];
+                }
+            }
+            if (wv < 4) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) x1[K::X1_SP + 256 * wv + 16 * (4 * v + lg) + li] = sacc[v];
+            }
+            __syncthreads();
+
+            // ---- Cholesky S = L L^T (lane i holds row i), c = L^-1 (y - G w) ----
+            // Wave 0 factors S = L L^T (lane i holds row i).  Step k publishes column
+            // k and (L^-1 dy)'s running value through LDS; a wave's LDS accesses are
+            // performed in program order, so no barrier is needed inside the loop.
+            int ndd = nd;
+            if (wv == 0) {
+                double srow[16];
+#pragma unroll
+                for (int cc = 0; cc < 16; ++cc) srow[cc] = cc == li ? 1.0 : 0.0;
+#pragma unroll 1
+                for (int q = 0; q < 4; ++q) {
+#pragma unroll
+                    for (int cc = 0; cc < 16; ++cc) srow[cc] += x1[K::X1_SP + 256 * q + 16 * li + cc];
+                }
+                double cy = rowok ? dyi : 0.0;
+                double *col = x1 + K::X1_COL;
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    if (lg == 0) {
+                        col[li] = srow[k];
+                        col[16 + li] = cy;
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                    const double piv = col[k];
+                    if (k < ndd && !(piv > 0.0 && isfinite(piv))) ndd = k;
+                    const double lkk = sqrt(piv), inv = 1.0 / lkk;
+                    const double ck = col[16 + k] * inv;
+                    const double lik = srow[k] * inv;  // L[i][k] for i > k
+                    double ljk[16];
+#pragma unroll
+                    for (int j = k + 1; j < 16; ++j) ljk[j] = col[j] * inv;
+                    srow[k] = li == k ? lkk : (li > k ? lik : 0.0);
+                    if (li > k) cy -= lik * ck;
+#pragma unroll
+                    for (int j = k + 1; j < 16; ++j) srow[j] -= lik * ljk[j];
+                    if (lg == 0 && li == 0) {
+                        x1[K::X1_C + k] = k < ndd ? ck : 0.0;
+                        x1[K::X1_C + 16 + k] = k < ndd ? inv : 0.0;
+                    }
+                    __builtin_amdgcn_wave_barrier();  // this step's loads before the next step's stores
+                }
+                if (lg == 0) {
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) x1[K::X1_L + 16 * li + k] = srow[k];
+                }
+                if (li == 0 && lg == 0) x1[K::X1_COL] = (double)ndd;
+            }
+            // Z to LDS for the substitution (every read of G ended at the barrier above)
+#pragma unroll
+            for (int ups = 0; ups < UPW; ++ups) {
+                const int u = wv + NW * ups;
+                if (u < nur) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) x2[zpos(16 * u + 4 * v + lg, li)] = z[ups][v];
+                }
+            }
+            __syncthreads();
+            ndd = (int)x1[K::X1_COL];
+
+            // ---- T = Z L^-T (row kk per thread, in place) and dw = T c ----
+            if (tl < 16 * nur) {
+                // T[kk][j] = (Z[kk][j] - sum_{j2 < j} T[kk][j2] L[j][j2]) / L[j][j]; the
+                // reciprocal diagonal is 0 past ndd, which zeroes those columns
+                double tr[16];
+#pragma unroll
+                for (int j = 0; j < 16; ++j) tr[j] = x2[zpos(tl, j)];
+                double dw = 0.0;
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    double a0 = tr[j], a1 = 0.0;
+#pragma unroll
+                    for (int j2 = 0; j2 < j; j2 += 2) {
+                        a0 -= tr[j2] * x1[K::X1_L + 16 * j + j2];
+                        if (j2 + 1 < j) a1 -= tr[j2 + 1] * x1[K::X1_L + 16 * j + j2 + 1];
+                    }
+                    tr[j] = (a0 + a1) * x1[K::X1_C + 16 + j];
+                    dw += tr[j] * x1[K::X1_C + j];
+                }
+#pragma unroll
+                for (int j = 0; j < 16; ++j) x2[zpos(tl, j)] = tr[j];
+                x1[K::X1_DW + tl] = dw;
+            }
+            __syncthreads();
+
+            // ---- w += T c, P^-1 -= T T^T ----
+#pragma unroll
+            for (int ups = 0; ups < UPW; ++ups) {
+                const int u = wv + NW * ups;
+                if (u < nur) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) wr[ups][v] += x1[K::X1_DW + 16 * u + 4 * v + lg];
+                    double bt[4];
+#pragma unroll
+                    for (int ks = 0; ks < 4; ++ks) bt[ks] = x2[zpos(16 * u + li, 4 * ks + lg)];
+#pragma unroll
+                    for (int u2 = 0; u2 < NU; ++u2) {
+                        if (u2 < nur) {
+                            d4 acc = p[u2][ups];
+#pragma unroll
+                            for (int ks = 0; ks < 4; ++ks) acc = mma(-x2[zpos(16 * u2 + li, 4 * ks + lg)], bt[ks], acc);
+                            p[u2][ups] = acc;
+                        }
+                    }
+                }
+            }
+            i += ndd;
+            applied += ndd;
+            if (ndd < nd) {
+                flags |= FLAG_DENOMINATOR;
+                break;
+            }
+            if (nd < nblk) {
+                if (stop) {
+                    flags |= stop;
+                    break;
+                }
+                block_mode = false;
+                ring_ok = false;
+            }
+            continue;
+        }
+
+        // ================= one row (Algorithm 1) =================
+        float *sg_ring = ring;
+        if (!ring_ok) {
+            __syncthreads();  // X2 may still be read by a block step
+            const float *Gi = G0 + (i - i0) * (int64_t)m;
+#pragma unroll
+            for (int e = 0; e < PF; ++e) {
+                const int j = tl + K::NT * e;
+                if (j < MMAX) sg_ring[cur * MMAX + j] = j < m ? Gi[j] : 0.0f;
+            }
+            const float *Gn = Gi + m;
+#pragma unroll
+            for (int e = 0; e < PF; ++e) {
+                const int j = tl + K::NT * e;
+                pre[e] = (i + 1 < i1 && j < m) ? Gn[j] : 0.0f;
+            }
+            y_next = a.y[i];
+            ring_ok = true;
+            __syncthreads();
+        }
+        // Row i is in slot cur; row i+1 (in pre) goes to slot nxt, which row
+        // i-2 read two barriers ago; row i+2 is requested now.
+        const int nxt = cur == 2 ? 0 : cur + 1;
+        if (i + 1 < i1) {
+#pragma unroll
+            for (int e = 0; e < PF; ++e) {
+                const int j = tl + K::NT * e;
+                if (j < MMAX) sg_ring[nxt * MMAX + j] = pre[e];
+            }
+        }
+        if (i + 2 < i1) {
+            const float *Gn = G0 + (i + 2 - i0) * (int64_t)m;
+#pragma unroll
+            for (int e = 0; e < PF; ++e) {
+                const int j = tl + K::NT * e;
+                pre[e] = j < m ? Gn[j] : 0.0f;
+            }
+        }
+        const double yv = (double)y_next;
+        if (i + 1 < i1) y_next = a.y[i + 1];
+        const float *gcur = sg_ring + cur * MMAX;
+        double *sgam = x1 + K::X1_GAM, *szeta = x1 + K::X1_ZETA, *sred = x1 + K::X1_RED, *sgr = x1 + K::X1_GR;
+
+        // ---- A: gamma = Ct Gamma (rows k = pk + 16 b, 16-lane sums) ----
+        double gam[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) gam[b] = 0.0;
+#pragma unroll 1
+        for (int c4 = 0; c4 < cba4; ++c4) {
+            const int ph = 16 * c4 + pj, lc = ph ^ pk15;  // physical chunk of Ct rows k (k & 15 == pk & 15), logical chunk
+            const float4 gv = *reinterpret_cast<const float4 *>(gcur + 4 * lc);
+            const double g0 = gv.x, g1 = gv.y, g2v = gv.z, g3 = gv.w;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int k = pk + RS * b;
+                float4 v = *reinterpret_cast<const float4 *>(sct + (size_t)min(k, ra - 1) * MMAX + 4 * ph);
+                if (k >= ra) v = make_float4(0.f, 0.f, 0.f, 0.f);
+                gam[b] += (double)v.x * g0;
+                gam[b] += (double)v.y * g1;
+                gam[b] += (double)v.z * g2v;
+                gam[b] += (double)v.w * g3;
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            gam[b] = sum16(gam[b]);
+            if (pj == 0) sgam[pk + RS * b] = gam[b];
+        }
+        __syncthreads();
+
+        // ---- B: C^T gamma, zeta = P^-1 gamma, gamma^T w per column tile ----
+        const int nur = (r + 15) / 16;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0}, zacc[2] = {0.0, 0.0};
+#pragma unroll
+        for (int u2 = 0; u2 < NU; ++u2) {
+            if (u2 < nur) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int s = 4 * u2 + v;
+                    const double gs = sgam[4 * s + lg];
+#pragma unroll
+                    for (int tau = 0; tau < TPW; ++tau) acc[tau] += f64_of(c[s][tau]) * gs;
+#pragma unroll
+                    for (int ups = 0; ups < UPW; ++ups) zacc[ups] += p[u2][ups][v] * gs;
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);  // one row tile at a time: bounds the live conversions
+        }
+        double dyp = 0.0;
+#pragma unroll
+        for (int ups = 0; ups < UPW; ++ups)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) dyp += wr[ups][v] * sgam[16 * (wv + NW * ups) + 4 * v + lg];
+        const double tcol = scatter4(acc[0], acc[1], acc[2], acc[3]);  // (C^T gamma) of column 16 (w + 4 g) + i
+        const double tz = scatter4(zacc[0], zacc[1], dyp, 0.0);        // zeta (g < UPW) or gamma^T w (g == 2)
+        double sp = 0.0, dp = 0.0, gw = 0.0, g2 = 0.0;
+        if (lg < TPW && wv + NW * lg < NTT) {
+            const int col = 16 * (wv + NW * lg) + li;
+            const double gc = (double)gcur[col];
+            const double v = gc - tcol;
+            sgr[col] = v;
+            sp = v * v;
+            g2 = gc * gc;
+        }
+        if (lg < UPW) {
+            const int kk = 16 * (wv + NW * lg) + li;
+            szeta[kk] = tz;
+            dp = tz * sgam[kk];
+        }
+        if (lg == 2 && li == 0) gw = tz;
+        block_sum4<NW>(sp, dp, gw, g2, sred);
+        if (!isfinite(g2) || !isfinite(yv)) {
+            flags |= FLAG_NONFINITE;
+            break;
+        }
+        const double eps = a.eps >= 0.0 ? a.eps : ((double)m * m * r + (double)m * r + (double)m) * 0x1p-52;
+        const double nr = sqrt(sp), ng = sqrt(g2);
+        const bool dependent = (sp == 0.0) || (nr < eps) || (nr < eps * ng);
+
+        if (dependent) {
+            if (r > 0) {
+                const double d = 1.0 + dp;
+                if (!(d > 0.0) || !isfinite(d)) {
+                    flags |= FLAG_DENOMINATOR;
+                    break;
+                }
+                const double inv_d = 1.0 / d;
+                const double f = (yv - gw) * inv_d;
+#pragma unroll
+                for (int ups = 0; ups < UPW; ++ups) {
+                    const double zc = szeta[16 * (wv + NW * ups) + li] * inv_d;
+#pragma unroll
+                    for (int u2 = 0; u2 < NU; ++u2) {
+                        if (u2 < nur) {
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) p[u2][ups][v] -= szeta[16 * u2 + 4 * v + lg] * zc;
+                        }
+                    }
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) wr[ups][v] += szeta[16 * (wv + NW * ups) + 4 * v + lg] * f;
+                }
+            }
+            block_mode = use_blocks;
+        } else {
+            if (r == rmax) {
+                flags |= FLAG_RANK_CAPACITY;
+                break;
+            }
+            double s_use = sp;
+            if (reproject && r > 0) {
+                // second pass ("twice is enough"): gamma2 = Ct Gamma_r, Gamma_r -= C^T gamma2
+                double gam2[NB];
+#pragma unroll
+                for (int b = 0; b < NB; ++b) gam2[b] = 0.0;
+#pragma unroll 1
+                for (int c4 = 0; c4 < cba4; ++c4) {
+                    const int ph = 16 * c4 + pj, lc = ph ^ pk15;
+                    const double r0 = sgr[4 * lc], r1 = sgr[4 * lc + 1], r2 = sgr[4 * lc + 2], r3 = sgr[4 * lc + 3];
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        const int k = pk + RS * b;
+                        float4 v = *reinterpret_cast<const float4 *>(sct + (size_t)min(k, ra - 1) * MMAX + 4 * ph);
+                        if (k >= ra) v = make_float4(0.f, 0.f, 0.f, 0.f);
+                        gam2[b] += (double)v.x * r0 + (double)v.y * r1 + (double)v.z * r2 + (double)v.w * r3;
+                    }
+                }
+                // every read of sgam (zeta, gamma^T w) ended before the last barrier
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    gam2[b] = sum16(gam2[b]);
+                    if (pj == 0) sgam[pk + RS * b] = gam2[b];
+                    gam[b] += gam2[b];
+                }
+                __syncthreads();
+                double acc2[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int u2 = 0; u2 < NU; ++u2) {
+                    if (u2 < nur) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int s = 4 * u2 + v;
+                            const double gs = sgam[4 * s + lg];
+#pragma unroll
+                            for (int tau = 0; tau < TPW; ++tau) acc2[tau] += f64_of(c[s][tau]) * gs;
+                        }
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                const double tcol2 = scatter4(acc2[0], acc2[1], acc2[2], acc2[3]);
+                double sp2 = 0.0, u0 = 0.0, u1 = 0.0, u3 = 0.0;
+                if (lg < TPW && wv + NW * lg < NTT) {
+                    const int col = 16 * (wv + NW * lg) + li;
+                    const double v = sgr[col] - tcol2;
+                    sgr[col] = v;
+                    sp2 = v * v;
+                }
+                block_sum4<NW>(sp2, u0, u1, u3, sred);
+                s_use = sp2;
+            }
+            const double inv_s = 1.0 / s_use;
+            // Ct <- Ct - gamma K^T on rows k < r (K = Gamma_r / ||Gamma_r||^2)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int k = pk + RS * b;
+                if (k < r) {
+                    const float gb = (float)gam[b];
+#pragma unroll 1
+                    for (int c4 = 0; c4 < cba4; ++c4) {
+                        const int ph = 16 * c4 + pj, lc = ph ^ pk15;
+                        float4 *p4 = reinterpret_cast<float4 *>(sct + (size_t)k * MMAX + 4 * ph);
+                        float4 v = *p4;
+                        v.x = fmaf(-gb, (float)(sgr[4 * lc] * inv_s), v.x);
+                        v.y = fmaf(-gb, (float)(sgr[4 * lc + 1] * inv_s), v.y);
+                        v.z = fmaf(-gb, (float)(sgr[4 * lc + 2] * inv_s), v.z);
+                        v.w = fmaf(-gb, (float)(sgr[4 * lc + 3] * inv_s), v.w);
+                        *p4 = v;
+                    }
+                }
+            }
+            // append: row r of Ct (K^T) and of C (Gamma^T), P^-1[r][r] = 1, w[r] = y
+            if (tl < CH) {
+                const float4 kv = make_float4((float)(sgr[4 * tl] * inv_s), (float)(sgr[4 * tl + 1] * inv_s),
+                                              (float)(sgr[4 * tl + 2] * inv_s), (float)(sgr[4 * tl + 3] * inv_s));
+                *reinterpret_cast<float4 *>(sct + (size_t)r * MMAX + 4 * (tl ^ (r & 15))) = kv;
+            }
+            if (lg == (r & 3)) {
+#pragma unroll
+                for (int s = 0; s < 4 * NU; ++s)
+                    if (s == (r >> 2)) {
+#pragma unroll
+                        for (int tau = 0; tau < TPW; ++tau)
+                            if (wv + NW * tau < NTT) c[s][tau] = gcur[16 * (wv + NW * tau) + li];
+                    }
+            }
+#pragma unroll
+            for (int ups = 0; ups < UPW; ++ups) {
+                const int u = wv + NW * ups;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    if (16 * u + 4 * v + lg == r) {
+                        wr[ups][v] = yv;
+#pragma unroll
+                        for (int u2 = 0; u2 < NU; ++u2)
+                            if (u2 == u && li == (r & 15)) p[u2][ups][v] = 1.0;
+                    }
+                }
+            }
+            r += 1;
+            __syncthreads();
+        }
+        ++i;
+        ++applied;
+        cur = nxt;
+    }
+
+    // ---- write the state back ------------------------------------------------
+    // The stores use freshly derived addresses (opaque copies of the strides and
+    // the lane id), so the compiler does not keep the load-time addresses of all
+    // register-resident state live across the row loop.
+    __syncthreads();
+    int ldm_w = ldm, rmax_w = rmax, lane_w = lane;
+    asm volatile("" : "+s"(ldm_w), "+s"(rmax_w), "+v"(lane_w));
+    const int li_w = lane_w & 15, lg_w = lane_w >> 4;
+    for (int idx = t; idx < ra * CH; idx += K::NT) {
+        const int k = idx / CH, cc = idx - k * CH;
+        if (k < r) {
+            const float4 v = *reinterpret_cast<const float4 *>(sct + (size_t)k * MMAX + 4 * (cc ^ (k & 15)));
+            const float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (4 * cc + e < m) Cg[(size_t)(rmax_w + k) * ldm_w + 4 * cc + e] = vv[e];
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < 4 * NU; ++s)
+#pragma unroll
+        for (int tau = 0; tau < TPW; ++tau) {
+            const int row = 4 * s + lg_w, col = 16 * (wv + NW * tau) + li_w;
+            if (row < r && col < m) Cg[(size_t)row * ldm_w + col] = c[s][tau];
+        }
+#pragma unroll
+    for (int ups = 0; ups < UPW; ++ups) {
+        const int col = 16 * (wv + NW * ups) + li_w;
+#pragma unroll
+        for (int u2 = 0; u2 < NU; ++u2)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = 16 * u2 + 4 * v + lg_w;
+                if (row < r && col < r) Pg[(size_t)row * rmax_w + col] = p[u2][ups][v];
+            }
+        if (li_w == 0) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int kk = 16 * (wv + NW * ups) + 4 * v + lg_w;
+                if (kk < r) wg[kk] = wr[ups][v];
+            }
+        }
+    }
+    if (t == 0) {
+        M->r = r;
+        M->flags = flags;
+        M->rows_seen += applied;
+    }
+    __syncthreads();
+}
+
+template <class K>
+size_t lds_bytes(int ra) {
+    return sizeof(float) * (size_t)ra * K::MMAX + sizeof(double) * (size_t)(K::X1_D + K::X2_D);
+}
+
+// Rows of Ct reserved in LDS: r_max rounded up to whole 16-row tiles.
+inline int rows16(int r_max) { return (r_max + 15) / 16 * 16; }
+
+using F0 = MF<64, 128, 4>;
+using F1 = MF<128, 128, 8>;
+using F2 = MF<64, 192, 4>;
+using F3 = MF<128, 192, 8>;
+using F4 = MF<64, 256, 4>;
+using F5 = MF<128, 256, 8>;
+
+template <class K>
+bool fits_k(int m, int r_max) {
+    return m <= K::MMAX && r_max <= K::RMAX && lds_bytes<K>(rows16(r_max)) <= 160 * 1024;
+}
+template <class K>
+hipError_t prepare_k(int r_max) {
+    const size_t lds = lds_bytes<K>(rows16(r_max));
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_push_mf<K>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+template <class K>
+hipError_t launch_k(const PushArgs<float> &a, int r_max, hipStream_t s) {
+    const int ra = rows16(r_max);
+    const size_t lds = lds_bytes<K>(ra);
+    if (lds > 160 * 1024 || ra > K::RMAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_push_mf<K>, dim3(a.n_order), dim3(K::NT), lds, s, a, ra);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int mf_choose(int m, int r_max) {
+    if (fits_k<F0>(m, r_max)) return 0;
+    if (fits_k<F1>(m, r_max)) return 1;
+    if (fits_k<F2>(m, r_max)) return 2;
+    if (fits_k<F3>(m, r_max)) return 3;
+    if (fits_k<F4>(m, r_max)) return 4;
+    if (fits_k<F5>(m, r_max)) return 5;
+    return -1;
+}
+
+int mf_rmax(int v) {
+    switch (v) {
+        case 0: return F0::RMAX;
+        case 1: return F1::RMAX;
+        case 2: return F2::RMAX;
+        case 3: return F3::RMAX;
+        case 4: return F4::RMAX;
+        case 5: return F5::RMAX;
+    }
+    return 0;
+}
+
+hipError_t mf_prepare(int v, int r_max) {
+    switch (v) {
+        case 0: return prepare_k<F0>(r_max);
+        case 1: return prepare_k<F1>(r_max);
+        case 2: return prepare_k<F2>(r_max);
+        case 3: return prepare_k<F3>(r_max);
+        case 4: return prepare_k<F4>(r_max);
+        case 5: return prepare_k<F5>(r_max);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t mf_launch(int v, const PushArgs<float> &a, int r_max, hipStream_t s) {
+    switch (v) {
+        case 0: return launch_k<F0>(a, r_max, s);
+        case 1: return launch_k<F1>(a, r_max, s);
+        case 2: return launch_k<F2>(a, r_max, s);
+        case 3: return launch_k<F3>(a, r_max, s);
+        case 4: return launch_k<F4>(a, r_max, s);
+        case 5: return launch_k<F5>(a, r_max, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace rg

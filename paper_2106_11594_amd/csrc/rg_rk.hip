@@ -26,6 +26,7 @@
 // Every branch condition is a workgroup-wide value (reduced through LDS), so
 // all waves take the same path and meet the same barriers.
 #include "rg_classes.h"
+#include "rg_lanes.h"
 
 namespace rg {
 namespace {
@@ -46,67 +47,6 @@ struct Cls {
     static constexpr int PF = (MMAX + NT - 1) / NT;
     static_assert(PK % 4 == 0, "row-groups come in whole waves");
 };
-
-// Cross-lane sums of doubles without LDS: DPP within a 16-lane row, gfx950
-// permlane swaps between rows.  Each step adds two operands in an order that
-// is the same on both lanes of a pair, so every lane ends with the same bits.
-__device__ inline double from_halves(int lo, int hi) {
-    return __hiloint2double(hi, lo);
-}
-template <int CTRL>
-__device__ inline double dpp(double v) {
-    const int lo = __double2loint(v), hi = __double2hiint(v);
-    return from_halves(__builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false),
-                       __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false));
-}
-// Sum over the 16 lanes of a DPP row: xor 1, xor 2 (quad_perm), then the
-// half-row and row mirrors pair the quads and the half-rows.
-__device__ inline double sum16(double v) {
-    v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]
-    v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]
-    v += dpp<0x141>(v);  // row_half_mirror
-    v += dpp<0x140>(v);  // row_mirror
-    return v;
-}
-// Sum over the 4 DPP rows of a wave (same lane pj): permlane16_swap pairs
-// rows (0,1) and (2,3), permlane32_swap pairs the two halves.
-__device__ inline double sum_rows(double v) {
-    {
-        const int lo = __double2loint(v), hi = __double2hiint(v);
-        const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
-        const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
-        v = from_halves(a[0], b[0]) + from_halves(a[1], b[1]);
-    }
-    {
-        const int lo = __double2loint(v), hi = __double2hiint(v);
-        const auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
-        const auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
-        v = from_halves(a[0], b[0]) + from_halves(a[1], b[1]);
-    }
-    return v;
-}
-__device__ inline double sum64(double v) { return sum_rows(sum16(v)); }
-
-// Reduce-scatter of four values over the 4 DPP rows of a wave, pairing two
-// different values per swap: permlane32_swap(a, b) gives rows (a0, a1, b0, b1)
-// and (a2, a3, b2, b3); permlane16_swap(a, b) gives (a0, b0, a2, b2) and
-// (a1, b1, a3, b3).  Returns, on row q of the wave, the total over the 4 rows
-// of v[q].
-__device__ inline double swap_add32(double a, double b) {
-    const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(a), __double2loint(b), false, false);
-    const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(a), __double2hiint(b), false, false);
-    return from_halves(lo[0], hi[0]) + from_halves(lo[1], hi[1]);
-}
-__device__ inline double swap_add16(double a, double b) {
-    const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(a), __double2loint(b), false, false);
-    const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(a), __double2hiint(b), false, false);
-    return from_halves(lo[0], hi[0]) + from_halves(lo[1], hi[1]);
-}
-__device__ inline double scatter4(double v0, double v1, double v2, double v3) {
-    // rows 0,1 now hold partials of v0 / v1, rows 2,3 of v2 / v3
-    const double u0 = swap_add32(v0, v2), u1 = swap_add32(v1, v3);
-    return swap_add16(u0, u1);
-}
 
 // Phase B of a row: this thread's partial sums over its rows K(pk) of
 //   q_j   = sum_k C[k][j] gamma_k          (columns J(pj))
@@ -199,7 +139,7 @@ __global__ void __launch_bounds__(K::NT) k_push_rk(PushArgs<float> a, int rows_a
     double *szeta = sgam + RMAX;                         // RMAX
     double *sred = szeta + RMAX;                         // 2 NW
 
-    const int t = threadIdx.x, pj = t & 15, pk = t >> 4, lane = t & 63, wv = t >> 6;
+    const int t = threadIdx.x, pj = t & 15, pk = t >> 4;
     const int b_id = a.order[blockIdx.x];
     StreamMeta *M = a.meta + b_id;
     const int m = M->m, rmax = M->r_max, ldm = M->ldm;
@@ -529,15 +469,11 @@ __global__ void __launch_bounds__(K::NT) k_push_rk(PushArgs<float> a, int rows_a
     __syncthreads();
 }
 
-// The size classes (PK, RB, CB4): RMAX = PK*RB rows, MMAX = 64*CB4 columns.
+// Row-by-row size classes (PK, RB, CB4): RMAX = PK*RB rows, MMAX = 64*CB4
+// columns.  Larger streams go to the blocked kernel (rg_mf.hip).
 using C0 = Cls<4, 3, 1>;
 using C1 = Cls<4, 9, 1>;
 using C2 = Cls<16, 2, 2>;
-using C3 = Cls<16, 5, 2>;
-using C4 = Cls<16, 4, 3>;
-using C5 = Cls<16, 7, 3>;
-using C6 = Cls<16, 4, 4>;
-using C7 = Cls<16, 8, 4>;
 
 template <class K>
 size_t lds_bytes(int rows_alloc) {
@@ -569,18 +505,14 @@ hipError_t launch(const PushArgs<float> &a, int rows_alloc, hipStream_t s) {
 
 }  // namespace
 
+// Classes 0..2 are this file's kernel, 3..8 the blocked kernel's variants 0..5.
 int class_rmax(int cls) {
     switch (cls) {
         case 0: return C0::RMAX;
         case 1: return C1::RMAX;
         case 2: return C2::RMAX;
-        case 3: return C3::RMAX;
-        case 4: return C4::RMAX;
-        case 5: return C5::RMAX;
-        case 6: return C6::RMAX;
-        case 7: return C7::RMAX;
     }
-    return 0;
+    return cls >= 3 ? mf_rmax(cls - 3) : 0;
 }
 
 int choose_class(int m, int r_max, int dtype) {
@@ -588,12 +520,8 @@ int choose_class(int m, int r_max, int dtype) {
     if (fits<C0>(m, r_max)) return 0;
     if (fits<C1>(m, r_max)) return 1;
     if (fits<C2>(m, r_max)) return 2;
-    if (fits<C3>(m, r_max)) return 3;
-    if (fits<C4>(m, r_max)) return 4;
-    if (fits<C5>(m, r_max)) return 5;
-    if (fits<C6>(m, r_max)) return 6;
-    if (fits<C7>(m, r_max)) return 7;
-    return -1;
+    const int v = mf_choose(m, r_max);
+    return v >= 0 ? 3 + v : -1;
 }
 
 hipError_t prepare_class(int cls, int rows_alloc) {
@@ -601,13 +529,8 @@ hipError_t prepare_class(int cls, int rows_alloc) {
         case 0: return prepare<C0>(rows_alloc);
         case 1: return prepare<C1>(rows_alloc);
         case 2: return prepare<C2>(rows_alloc);
-        case 3: return prepare<C3>(rows_alloc);
-        case 4: return prepare<C4>(rows_alloc);
-        case 5: return prepare<C5>(rows_alloc);
-        case 6: return prepare<C6>(rows_alloc);
-        case 7: return prepare<C7>(rows_alloc);
     }
-    return hipErrorInvalidValue;
+    return cls >= 3 ? mf_prepare(cls - 3, rows_alloc) : hipErrorInvalidValue;
 }
 
 template <>
@@ -616,13 +539,8 @@ hipError_t launch_push_class<float>(int cls, const PushArgs<float> &a, int rows_
         case 0: return launch<C0>(a, rows_alloc, s);
         case 1: return launch<C1>(a, rows_alloc, s);
         case 2: return launch<C2>(a, rows_alloc, s);
-        case 3: return launch<C3>(a, rows_alloc, s);
-        case 4: return launch<C4>(a, rows_alloc, s);
-        case 5: return launch<C5>(a, rows_alloc, s);
-        case 6: return launch<C6>(a, rows_alloc, s);
-        case 7: return launch<C7>(a, rows_alloc, s);
     }
-    return hipErrorInvalidValue;
+    return cls >= 3 ? mf_launch(cls - 3, a, rows_alloc, s) : hipErrorInvalidValue;
 }
 
 template <>

@@ -1,0 +1,131 @@
+"""The blocked variant (dependent rows applied 16 at a time on the matrix
+cores) against the row-by-row path (RG_OPT_ROW_BY_ROW) and the oracle, on
+stream shapes that use the blocked kernel's variants, including the rows
+where a block has to stop: an independent row inside a block, a non-finite
+row, the rank capacity, zero rows and ragged tails."""
+import numpy as np
+import pytest
+
+from oracle import ref_c
+from paper_2106_11594_amd import workloads as W
+
+# (m, r_max) pairs that select each variant of the blocked kernel
+VARIANT_SHAPES = [(100, 44), (120, 100), (170, 60), (190, 120), (250, 40), (256, 128)]
+
+
+def _rel(x, xo):
+    return float(np.linalg.norm(x - xo) / max(np.linalg.norm(xo), 1e-300))
+
+
+def _kappa_tol(C):
+    kap = float(np.linalg.cond(C)) if C.shape[0] else 1.0
+    return (1e-5 if kap <= 1e3 else 0.1 * kap * 2.0 ** -23), kap
+
+
+def _solve(A, Y, r_max, flags=0, chunks=None):
+    import torch
+    from paper_2106_11594_amd import rg
+    Ad = torch.from_numpy(np.ascontiguousarray(A, np.float32)).cuda()
+    Yd = torch.from_numpy(np.ascontiguousarray(Y, np.float32)).cuda()
+    h = rg.Solver(A.shape[1], r_max=r_max, dtype="f32", eps=1e-3, flags=flags)
+    bounds = [0] + list(chunks or []) + [A.shape[0]]
+    for c0, c1 in zip(bounds[:-1], bounds[1:]):
+        if c1 > c0:
+            h.push_rows(Ad[c0:c1].contiguous(), Yd[c0:c1].contiguous())
+    x = h.solution().double().cpu().numpy()
+    r, f = h.rank(), h.flags()
+    h.close()
+    return x, r, f
+
+
+def _f32(a):
+    return np.asarray(a, np.float32).astype(np.float64)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("m,r_max", VARIANT_SHAPES)
+def test_variant_blocked_vs_row_by_row_and_oracle(m, r_max):
+    from paper_2106_11594_amd import rg
+    rng = np.random.default_rng(m * 7 + r_max)
+    r = r_max - 4
+    A = W.lowrank_rows(rng, m, r, 3 * m + 37)  # ragged: not a multiple of 16 past the rank
+    Y, _ = W.targets(rng, A)
+    A, Y = _f32(A), _f32(Y)
+    xb, rb, fb = _solve(A, Y, r_max)
+    xr, rr, fr = _solve(A, Y, r_max, flags=rg.OPT_ROW_BY_ROW)
+    xo, ro, Co, *_ = ref_c.solve(A, Y, eps=1e-3, cap=r_max)
+    tol, kap = _kappa_tol(Co)
+    print("m=%d r_max=%d: rank %d/%d/%d, kappa %.3g, blocked %.2e, row-by-row %.2e, between %.2e"
+          % (m, r_max, rb, rr, ro, kap, _rel(xb, xo), _rel(xr, xo), _rel(xb, xr)), flush=True)
+    assert fb == fr == 0
+    assert rb == rr == ro == r
+    assert _rel(xb, xo) <= tol and _rel(xr, xo) <= tol
+    assert _rel(xb, xr) <= tol
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("m,r_max", [(150, 60), (240, 110)])
+def test_copies_and_combinations_stop_blocks(m, r_max):
+    """Copies and two-row combinations among fresh rows: independent rows
+    land inside blocks, which must stop there."""
+    from paper_2106_11594_amd import rg
+    s = W.large_stream(n=4 * r_max, m=m, r=r_max - 6, p_dup=0.3, p_comb=0.2, dtype="f32")
+    xb, rb, fb = _solve(s.A, s.Y, r_max, chunks=[37, 101])
+    xr, rr, fr = _solve(s.A, s.Y, r_max, flags=rg.OPT_ROW_BY_ROW)
+    xo, ro, Co, *_ = ref_c.solve(s.A, s.Y, eps=1e-3, cap=r_max)
+    tol, kap = _kappa_tol(Co)
+    assert fb == fr == 0 and rb == rr == ro
+    assert _rel(xb, xo) <= tol and _rel(xr, xo) <= tol
+
+
+@pytest.mark.gpu
+def test_nonfinite_row_inside_a_block():
+    rng = np.random.default_rng(11)
+    A = W.lowrank_rows(rng, 180, 40, 150)
+    Y, _ = W.targets(rng, A)
+    A, Y = _f32(A).copy(), _f32(Y)
+    A[97, 13] = np.nan  # past the rank, in the middle of a block
+    x, r, f = _solve(A, Y, 48)
+    xo, ro, *_ = ref_c.solve(A[:97], Y[:97], eps=1e-3, cap=48)
+    assert f == 0x1 and r == ro == 40
+    assert _rel(x, xo) <= 1e-5
+
+
+@pytest.mark.gpu
+def test_nonfinite_target_inside_a_block():
+    rng = np.random.default_rng(12)
+    A = W.lowrank_rows(rng, 200, 50, 160)
+    Y, _ = W.targets(rng, A)
+    A, Y = _f32(A), _f32(Y).copy()
+    Y[120] = np.inf
+    x, r, f = _solve(A, Y, 64)
+    xo, ro, *_ = ref_c.solve(A[:120], Y[:120], eps=1e-3, cap=64)
+    assert f == 0x1 and r == ro == 50
+    assert _rel(x, xo) <= 1e-5
+
+
+@pytest.mark.gpu
+def test_rank_capacity_in_blocked_variant():
+    rng = np.random.default_rng(13)
+    A = W.lowrank_rows(rng, 200, 90, 200)
+    Y, _ = W.targets(rng, A)
+    A, Y = _f32(A), _f32(Y)
+    x, r, f = _solve(A, Y, 70)
+    xo, ro, *_ = ref_c.solve(A[:70], Y[:70], eps=1e-3, cap=70)
+    assert f == 0x2 and r == 70
+    assert _rel(x, xo) <= 1e-5
+
+
+@pytest.mark.gpu
+def test_zero_rows_and_incremental_pushes():
+    rng = np.random.default_rng(14)
+    A = W.lowrank_rows(rng, 130, 30, 200)
+    Y, _ = W.targets(rng, A)
+    A, Y = _f32(A).copy(), _f32(Y).copy()
+    A[60:75] = 0.0
+    Y[60:75] = 0.0
+    x1, r1, f1 = _solve(A, Y, 40)
+    x2, r2, f2 = _solve(A, Y, 40, chunks=[1, 31, 32, 47, 63, 64, 150, 199])
+    xo, ro, *_ = ref_c.solve(A, Y, eps=1e-3, cap=40)
+    assert f1 == f2 == 0 and r1 == r2 == ro == 30
+    assert _rel(x1, xo) <= 1e-5 and _rel(x2, xo) <= 1e-5
