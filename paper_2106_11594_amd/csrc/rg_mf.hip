@@ -50,6 +50,16 @@ __device__ inline d4 mma(double a, double b, d4 c) {
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
+// 1/sqrt(x) in FP64: the hardware estimate refined by two Newton steps
+// y <- y (3 - x y^2) / 2, each of which doubles the number of correct bits.
+__device__ inline double rsqrt_f64(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    y = fma(y, fma(-h * y, y, 0.5), y);
+    y = fma(y, fma(-h * y, y, 0.5), y);
+    return y;
+}
+
 // FP64 value of a register-resident FP32 state element.  The empty asm keeps
 // the compiler from hoisting the conversion out of the row loop, which would
 // keep an FP64 copy of all of C live and double its register footprint.
@@ -188,6 +198,28 @@ __global__ void __launch_bounds__(K::NT) k_push_mf(PushArgs<float> a, int ra) {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
 
+    // Block rows come through registers: pfv holds rows pf_i .. pf_i + 15 as
+    // float4 chunks (thread tl has chunks tl + NT e), pfy the target of row
+    // pf_i + (lane & 15).
+    constexpr int PFB = (KB * CH + K::NT - 1) / K::NT;
+    float4 pfv[PFB];
+    float pfy = 0.0f;
+    int64_t pf_i = -1;
+    auto fetch_block = [&](const float *src0, const float *ysrc, int nrows, int mm, int tid, float4 (&dst)[PFB], float &ydst) {
+#pragma unroll
+        for (int e = 0; e < PFB; ++e) {
+            const int idx = tid + K::NT * e, j = idx / CH, cc = idx - j * CH;
+            const float *src = src0 + (int64_t)j * mm;
+            float v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int col = 4 * cc + q;
+                v[q] = (idx < KB * CH && j < nrows && col < mm) ? src[col] : 0.0f;
+            }
+            dst[e] = make_float4(v[0], v[1], v[2], v[3]);
+        }
+        ydst = (tid & 15) < nrows ? ysrc[tid & 15] : 0.0f;
+    };
     const bool reproject = !(a.opts & OPT_NO_REPROJECT);
     const bool use_blocks = !(a.opts & OPT_ROW_BY_ROW);
     int64_t i = i0, applied = 0;
@@ -210,19 +242,17 @@ __global__ void __launch_bounds__(K::NT) k_push_mf(PushArgs<float> a, int ra) {
             // ================= block of up to KB rows =================
             __syncthreads();  // earlier readers of X1 / X2 are done
             const int nblk = (int)min((int64_t)KB, i1 - i);
-            for (int idx = tl; idx < KB * CH; idx += K::NT) {
-                const int j = idx / CH, cc = idx - j * CH;
-                float v[4];
-                const float *src = G0 + (i - i0 + j) * (int64_t)m;
+            if (pf_i != i) fetch_block(G0 + (i - i0) * (int64_t)m, a.y + i, nblk, m, tl, pfv, pfy);
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int col = 4 * cc + e;
-                    v[e] = (j < nblk && col < m) ? src[col] : 0.0f;
-                }
-                *reinterpret_cast<float4 *>(x1f + j * MMAX + 4 * (cc ^ j)) = make_float4(v[0], v[1], v[2], v[3]);
+            for (int e = 0; e < PFB; ++e) {
+                const int idx = tl + K::NT * e, j = idx / CH, cc = idx - j * CH;
+                if (idx < KB * CH) *reinterpret_cast<float4 *>(x1f + j * MMAX + 4 * (cc ^ j)) = pfv[e];
             }
-            const double yrow = li < nblk ? (double)a.y[i + li] : 0.0;
+            const double yrow = (double)pfy;
             __syncthreads();
+            // the next block's rows are requested now (used if all of this block applies)
+            pf_i = i + nblk;
+            if (pf_i < i1) fetch_block(G0 + (pf_i - i0) * (int64_t)m, a.y + pf_i, (int)min((int64_t)KB, i1 - pf_i), m, tl, pfv, pfy);
 
             // ---- G = Gamma_blk Ct^T: tiles u = wv + 4 ups of G^T ----
             const int nur = (r + 15) / 16;
@@ -399,9 +429,10 @@ __global__ void __launch_bounds__(K::NT) k_push_mf(PushArgs<float> a, int ra) {
 
             // ---- Cholesky S = L L^T (lane i holds row i), c = L^-1 (y - G w) ----
             // Wave 0 factors S = L L^T (lane i holds row i).  Step k publishes column
-            // k and (L^-1 dy)'s running value through LDS; a wave's LDS accesses are
-            // performed in program order, so no barrier is needed inside the loop.
-            int ndd = nd;
+            // k and the running value of L^-1 (y - G w) through LDS; LDS accesses of
+            // one wave are performed in program order, so the wave needs no barrier.
+            // A pivot that is not positive and finite ends the prefix of applied rows
+            // (ndd); what follows it is computed but never used.
             if (wv == 0) {
                 double srow[16];
 #pragma unroll
@@ -412,37 +443,49 @@ __global__ void __launch_bounds__(K::NT) k_push_mf(PushArgs<float> a, int ra) {
                     for (int cc = 0; cc < 16; ++cc) srow[cc] += x1[K::X1_SP + 256 * q + 16 * li + cc];
                 }
                 double cy = rowok ? dyi : 0.0;
+                double mypiv = 1.0, myc = 0.0, myinv = 0.0;
                 double *col = x1 + K::X1_COL;
 #pragma unroll
                 for (int k = 0; k < 16; ++k) {
-                    if (lg == 0) {
-                        col[li] = srow[k];
-                        col[16 + li] = cy;
-                    }
+                    col[li] = srow[k];
+                    col[16 + li] = cy;
                     __builtin_amdgcn_wave_barrier();
-                    const double piv = col[k];
-                    if (k < ndd && !(piv > 0.0 && isfinite(piv))) ndd = k;
-                    const double lkk = sqrt(piv), inv = 1.0 / lkk;
-                    const double ck = col[16 + k] * inv;
+                    double cv[16];  // column k, read with wide loads issued back to back
+#pragma unroll
+                    for (int q = k / 2; q < 8; ++q) {
+                        const double2 v2 = reinterpret_cast<const double2 *>(col)[q];
+                        cv[2 * q] = v2.x;
+                        cv[2 * q + 1] = v2.y;
+                    }
+                    const double cyk = col[16 + k];
+                    __builtin_amdgcn_wave_barrier();  // this step's loads before the next step's stores
+                    const double piv = cv[k];
+                    const double inv = rsqrt_f64(piv), lkk = piv * inv;
+                    const double ck = cyk * inv;
                     const double lik = srow[k] * inv;  // L[i][k] for i > k
                     double ljk[16];
 #pragma unroll
-                    for (int j = k + 1; j < 16; ++j) ljk[j] = col[j] * inv;
+                    for (int j = k + 1; j < 16; ++j) ljk[j] = cv[j] * inv;
+                    if (li == k) {
+                        mypiv = piv;
+                        myc = ck;
+                        myinv = inv;
+                    }
                     srow[k] = li == k ? lkk : (li > k ? lik : 0.0);
                     if (li > k) cy -= lik * ck;
 #pragma unroll
                     for (int j = k + 1; j < 16; ++j) srow[j] -= lik * ljk[j];
-                    if (lg == 0 && li == 0) {
-                        x1[K::X1_C + k] = k < ndd ? ck : 0.0;
-                        x1[K::X1_C + 16 + k] = k < ndd ? inv : 0.0;
-                    }
-                    __builtin_amdgcn_wave_barrier();  // this step's loads before the next step's stores
                 }
+                const uint64_t badp = __ballot(!(mypiv > 0.0 && isfinite(mypiv))) & 0xFFFFull;
+                const int nbad = badp ? (int)__builtin_ctzll(badp) : 16;
+                const int nk = nbad < nd ? nbad : nd;
                 if (lg == 0) {
 #pragma unroll
                     for (int k = 0; k < 16; ++k) x1[K::X1_L + 16 * li + k] = srow[k];
+                    x1[K::X1_C + li] = li < nk ? myc : 0.0;
+                    x1[K::X1_C + 16 + li] = li < nk ? myinv : 0.0;
                 }
-                if (li == 0 && lg == 0) x1[K::X1_COL] = (double)ndd;
+                if (li == 0 && lg == 0) x1[K::X1_COL] = (double)nk;
             }
             // Z to LDS for the substitution (every read of G ended at the barrier above)
 #pragma unroll
@@ -454,12 +497,12 @@ __global__ void __launch_bounds__(K::NT) k_push_mf(PushArgs<float> a, int ra) {
                 }
             }
             __syncthreads();
-            ndd = (int)x1[K::X1_COL];
+            const int ndd = (int)x1[K::X1_COL];
 
             // ---- T = Z L^-T (row kk per thread, in place) and dw = T c ----
             if (tl < 16 * nur) {
-                // T[kk][j] = (Z[kk][j] - sum_{j2 < j} T[kk][j2] L[j][j2]) / L[j][j]; the
-                // reciprocal diagonal is 0 past ndd, which zeroes those columns
+                // T[kk][j] = (Z[kk][j] - sum_{j2 < j} T[kk][j2] L[j][j2]) / L[j][j]; columns
+                // from ndd on are zero (a failed pivot leaves non-finite values there)
                 double tr[16];
 #pragma unroll
                 for (int j = 0; j < 16; ++j) tr[j] = x2[zpos(tl, j)];
@@ -467,12 +510,14 @@ __global__ void __launch_bounds__(K::NT) k_push_mf(PushArgs<float> a, int ra) {
 #pragma unroll
                 for (int j = 0; j < 16; ++j) {
                     double a0 = tr[j], a1 = 0.0;
+                    const double2 *lrow = reinterpret_cast<const double2 *>(x1 + K::X1_L + 16 * j);
 #pragma unroll
                     for (int j2 = 0; j2 < j; j2 += 2) {
-                        a0 -= tr[j2] * x1[K::X1_L + 16 * j + j2];
-                        if (j2 + 1 < j) a1 -= tr[j2 + 1] * x1[K::X1_L + 16 * j + j2 + 1];
+                        const double2 l2 = lrow[j2 / 2];
+                        a0 -= tr[j2] * l2.x;
+                        if (j2 + 1 < j) a1 -= tr[j2 + 1] * l2.y;
                     }
-                    tr[j] = (a0 + a1) * x1[K::X1_C + 16 + j];
+                    tr[j] = j < ndd ? (a0 + a1) * x1[K::X1_C + 16 + j] : 0.0;
                     dw += tr[j] * x1[K::X1_C + j];
                 }
 #pragma unroll
