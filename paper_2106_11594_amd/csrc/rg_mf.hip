@@ -7,7 +7,9 @@
 //         c of row k sits at physical chunk c ^ (k & 15), so that the 16 rows
 //         a matrix-core operand touches fall into different banks;
 //   C     registers, FP32: c[s][tau] = C[4s + g][16 (w + NW tau) + i]
-//         (the A operand of C^T for column tile w + NW tau, K-step s);
+//         (the A operand of C^T for column tile w + NW tau, K-step s); for
+//         RMAX = 128, where C and P^-1 would not both fit, C is read in the
+//         same pattern from the stream's state in global memory (L2);
 //   P^-1  registers, FP64, 16 x 16 output tiles (u', u) for the column tiles
 //         u = w + NW ups of this wave: p[u'][ups][v] = P^-1[16u' + 4v + g][16u + i];
 //   w     registers, FP64: wr[ups][v] = w[16 (w + NW ups) + 4v + g].
@@ -68,9 +70,12 @@ __device__ inline double f64_of(float v) {
     return (double)v;
 }
 
-template <int RMAX_, int MMAX_, int NW_>
+template <int RMAX_, int MMAX_, int NW_, bool CG_>
 struct MF {
     static constexpr int RMAX = RMAX_, MMAX = MMAX_, NW = NW_;
+    // CG: C is read from the stream's state in global memory (L2-resident)
+    // instead of registers; used where C and P^-1 together would not fit.
+    static constexpr bool CG = CG_;
     static_assert((RMAX == 64 || RMAX == 128) && (RMAX / 16) % NW == 0, "whole row tiles per wave");
     static_assert(MMAX % 64 == 0 && MMAX <= 256 && (NW == 4 || NW == 8), "4 or 8 waves");
     static constexpr int NT = 64 * NW;
@@ -169,14 +174,17 @@ __global__ void __launch_bounds__(K::NT) k_push_mf(PushArgs<float> a, int ra) {
         *reinterpret_cast<float4 *>(sct + (size_t)k * MMAX + 4 * (c ^ (k & 15))) = make_float4(v[0], v[1], v[2], v[3]);
     }
     const int li = lane & 15, lg = lane >> 4;
-    float c[4 * NU][TPW];
+    constexpr int NCS = K::CG ? 1 : 4 * NU, NCT = K::CG ? 1 : TPW;
+    float c[NCS][NCT];
+    if constexpr (!K::CG) {
 #pragma unroll
-    for (int s = 0; s < 4 * NU; ++s)
+        for (int s = 0; s < 4 * NU; ++s)
 #pragma unroll
-        for (int tau = 0; tau < TPW; ++tau) {
-            const int row = 4 * s + lg, col = 16 * (wv + NW * tau) + li;
-            c[s][tau] = (row < r && col < m) ? Cg[(size_t)row * ldm + col] : 0.0f;
-        }
+            for (int tau = 0; tau < TPW; ++tau) {
+                const int row = 4 * s + lg, col = 16 * (wv + NW * tau) + li;
+                c[s][tau] = (row < r && col < m) ? Cg[(size_t)row * ldm + col] : 0.0f;
+            }
+    }
     d4 p[NU][UPW];
     double wr[UPW][4];
 #pragma unroll
@@ -238,6 +246,15 @@ __global__ void __launch_bounds__(K::NT) k_push_mf(PushArgs<float> a, int ra) {
         asm volatile("" : "+v"(lane_l));
         const int li = lane_l & 15, lg = lane_l >> 4, tl = 64 * wv + lane_l;
         const int pk = tl >> 4, pj = tl & 15, pk15 = pk & 15;
+        // C[4s + g][16 (w + NW tau) + i] in FP64 (zero past the rank and past m)
+        auto cval = [&](int s, int tau) -> double {
+            if constexpr (K::CG) {
+                const int row = 4 * s + lg, col = 16 * (wv + NW * tau) + li;
+                return (row < r && col < m) ? (double)Cg[(size_t)row * ldm + col] : 0.0;
+            } else {
+                return f64_of(c[s][tau]);
+            }
+        };
         if (block_mode) {
             // ================= block of up to KB rows =================
             __syncthreads();  // earlier readers of X1 / X2 are done
@@ -333,7 +350,7 @@ __global__ void __launch_bounds__(K::NT) k_push_mf(PushArgs<float> a, int ra) {
 #pragma unroll
                             for (int v = 0; v < 4; ++v) {
                                 const int s = 4 * u2 + v;
-                                d = mma(f64_of(c[s][tau]), -x2[gpos<RMAX>(li, 4 * s + lg)], d);
+                                d = mma(cval(s, tau), -x2[gpos<RMAX>(li, 4 * s + lg)], d);
                             }
                         }
                     }
@@ -645,7 +662,7 @@ __global__ void __launch_bounds__(K::NT) k_push_mf(PushArgs<float> a, int ra) {
                     const int s = 4 * u2 + v;
                     const double gs = sgam[4 * s + lg];
 #pragma unroll
-                    for (int tau = 0; tau < TPW; ++tau) acc[tau] += f64_of(c[s][tau]) * gs;
+                    for (int tau = 0; tau < TPW; ++tau) acc[tau] += cval(s, tau) * gs;
 #pragma unroll
                     for (int ups = 0; ups < UPW; ++ups) zacc[ups] += p[u2][ups][v] * gs;
                 }
@@ -747,7 +764,7 @@ __global__ void __launch_bounds__(K::NT) k_push_mf(PushArgs<float> a, int ra) {
                             const int s = 4 * u2 + v;
                             const double gs = sgam[4 * s + lg];
 #pragma unroll
-                            for (int tau = 0; tau < TPW; ++tau) acc2[tau] += f64_of(c[s][tau]) * gs;
+                            for (int tau = 0; tau < TPW; ++tau) acc2[tau] += cval(s, tau) * gs;
                         }
                     }
                     __builtin_amdgcn_sched_barrier(0);
@@ -789,7 +806,10 @@ __global__ void __launch_bounds__(K::NT) k_push_mf(PushArgs<float> a, int ra) {
                                               (float)(sgr[4 * tl + 2] * inv_s), (float)(sgr[4 * tl + 3] * inv_s));
                 *reinterpret_cast<float4 *>(sct + (size_t)r * MMAX + 4 * (tl ^ (r & 15))) = kv;
             }
-            if (lg == (r & 3)) {
+            if constexpr (K::CG) {
+                // row r of C straight to the state; the barrier below makes it visible
+                for (int j = tl; j < m; j += K::NT) Cg[(size_t)r * ldm + j] = gcur[j];
+            } else if (lg == (r & 3)) {
 #pragma unroll
                 for (int s = 0; s < 4 * NU; ++s)
                     if (s == (r >> 2)) {
@@ -837,13 +857,15 @@ __global__ void __launch_bounds__(K::NT) k_push_mf(PushArgs<float> a, int ra) {
                 if (4 * cc + e < m) Cg[(size_t)(rmax_w + k) * ldm_w + 4 * cc + e] = vv[e];
         }
     }
+    if constexpr (!K::CG) {
 #pragma unroll
-    for (int s = 0; s < 4 * NU; ++s)
+        for (int s = 0; s < 4 * NU; ++s)
 #pragma unroll
-        for (int tau = 0; tau < TPW; ++tau) {
-            const int row = 4 * s + lg_w, col = 16 * (wv + NW * tau) + li_w;
-            if (row < r && col < m) Cg[(size_t)row * ldm_w + col] = c[s][tau];
-        }
+            for (int tau = 0; tau < TPW; ++tau) {
+                const int row = 4 * s + lg_w, col = 16 * (wv + NW * tau) + li_w;
+                if (row < r && col < m) Cg[(size_t)row * ldm_w + col] = c[s][tau];
+            }
+    }
 #pragma unroll
     for (int ups = 0; ups < UPW; ++ups) {
         const int col = 16 * (wv + NW * ups) + li_w;
@@ -878,12 +900,12 @@ size_t lds_bytes(int ra) {
 // Rows of Ct reserved in LDS: r_max rounded up to whole 16-row tiles.
 inline int rows16(int r_max) { return (r_max + 15) / 16 * 16; }
 
-using F0 = MF<64, 128, 4>;
-using F1 = MF<128, 128, 8>;
-using F2 = MF<64, 192, 4>;
-using F3 = MF<128, 192, 8>;
-using F4 = MF<64, 256, 4>;
-using F5 = MF<128, 256, 8>;
+using F0 = MF<64, 128, 4, false>;
+using F1 = MF<128, 128, 8, true>;
+using F2 = MF<64, 192, 4, false>;
+using F3 = MF<128, 192, 8, true>;
+using F4 = MF<64, 256, 4, false>;
+using F5 = MF<128, 256, 8, true>;
 
 template <class K>
 bool fits_k(int m, int r_max) {
