@@ -59,6 +59,8 @@ def main():
     ap.add_argument("--B", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
     ap.add_argument("--serial-classes", action="store_true", help="launch size classes one after another")
+    ap.add_argument("--default-classes", action="store_true",
+                    help="ignore the autotuned class rules (paper_2106_11594_amd/class_rules.json)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: the batched streams are independent and this build "
@@ -78,6 +80,10 @@ def main():
     rp = torch.from_numpy(bt.row_ptr).to(dev)
     ao = torch.from_numpy(bt.a_off).to(dev)
     r_max = headroom(bt.ms, bt.rs)
+    from paper_2106_11594_amd import autotune
+    rules = None if args.default_classes else autotune.load()
+    if rules:
+        rg.set_class_rules(rules)
     h = rg.Batch(bt.ms, r_max=r_max, dtype="f32", eps=1e-3,
                  flags=rg.OPT_SERIAL_CLASSES if args.serial_classes else 0)
     h.plan(bt.ns)
@@ -131,7 +137,8 @@ def main():
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "batched uneven streams: B=%d, m~U{16..256}, r~U{4..m/2}, n~U{m..8m}, "
                                   "FP32 state, FP64 rank test (eps 1e-3), rank capacity min(r+4, 128)" % bt.B,
-                      "streams": bt.B, "rows": rows},
+                      "streams": bt.B, "rows": rows,
+                      "class_placement": ("autotuned rules (%d)" % len(rules)) if rules else "default"},
            "roofline": roof}
 
     if not args.no_cpu:

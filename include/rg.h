@@ -165,6 +165,30 @@ rg_status rg_batch_get_state(rg_handle h, int32_t b, void *C, void *Ct, void *Pi
 rg_status rg_batch_adjoint(rg_handle h, const void *A, const void *Y, const int64_t *row_ptr,
                            const int64_t *a_off, const void *g, void *dA, void *dY);
 
+/* ---- kernel size classes (tuning) -------------------------------------- */
+
+/* FP32 streams run in one of rg_class_count() on-chip kernel classes, or in
+ * the global-memory kernel.  By default a stream takes the smallest class that
+ * holds it; a tuning tool can measure the classes and install rules instead. */
+int32_t rg_class_count(void);
+
+/* Shape of class cls: largest rank capacity, largest m, threads per stream
+ * (host outputs, each nullable).  RG_E_INVALID for cls out of range. */
+rg_status rg_class_info(int32_t cls, int32_t *r_max_cap, int32_t *m_cap, int32_t *threads);
+
+/* *fits (host) = 1 if class cls can hold a stream with m regressors and rank
+ * capacity r_max (including its on-chip memory at that capacity), else 0. */
+rg_status rg_class_fits(int32_t cls, int32_t m, int32_t r_max, int32_t *fits);
+
+/* Install process-wide placement rules, used by every later rg_init /
+ * rg_batch_init (handles already created keep their classes).  A stream with
+ * m regressors and capacity r_max takes the class of the first rule k with
+ * m <= m_hi[k] and r_max <= r_max_hi[k] whose class can hold it; cls[k] = -1
+ * selects the global-memory kernel.  Streams no rule places get the default.
+ * The arrays (host, n entries) are copied; n = 0 restores the default.  Not
+ * safe to call while another thread creates a handle. */
+rg_status rg_set_class_rules(const int32_t *m_hi, const int32_t *r_max_hi, const int32_t *cls, int32_t n);
+
 /* Device bytes the workspace of such a batch takes. */
 size_t rg_workspace_bytes(int32_t B, const int32_t *m, const int32_t *r_max, int32_t dtype);
 

@@ -210,6 +210,30 @@ const char *rg_status_string(rg_status s) {
     return "unknown status";
 }
 
+int32_t rg_class_count(void) { return RG_NUM_CLASSES; }
+
+rg_status rg_class_info(int32_t cls, int32_t *r_max_cap, int32_t *m_cap, int32_t *threads) {
+    if (cls < 0 || cls >= RG_NUM_CLASSES) return RG_E_INVALID;
+    if (r_max_cap) *r_max_cap = rg::class_rmax(cls);
+    if (m_cap) *m_cap = rg::class_mmax(cls);
+    if (threads) *threads = rg::class_threads(cls);
+    return RG_OK;
+}
+
+rg_status rg_class_fits(int32_t cls, int32_t m, int32_t r_max, int32_t *fits) {
+    if (!fits || cls < 0 || cls >= RG_NUM_CLASSES || m <= 0 || r_max <= 0) return RG_E_INVALID;
+    *fits = rg::class_fits(cls, m, r_max) ? 1 : 0;
+    return RG_OK;
+}
+
+rg_status rg_set_class_rules(const int32_t *m_hi, const int32_t *r_max_hi, const int32_t *cls, int32_t n) {
+    if (n < 0 || (n > 0 && (!m_hi || !r_max_hi || !cls))) return RG_E_INVALID;
+    for (int k = 0; k < n; ++k)
+        if (cls[k] < -1 || cls[k] >= RG_NUM_CLASSES) return RG_E_INVALID;
+    rg::set_class_rules(m_hi, r_max_hi, cls, n);
+    return RG_OK;
+}
+
 size_t rg_workspace_bytes(int32_t B, const int32_t *m, const int32_t *r_max, int32_t dtype) {
     if (B <= 0 || !m || (dtype != RG_F32 && dtype != RG_F64)) return 0;
     for (int b = 0; b < B; ++b)

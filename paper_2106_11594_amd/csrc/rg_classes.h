@@ -18,8 +18,18 @@ hipError_t prepare_class(int cls, int rows_alloc);
 // r_max among them (rows of Ct reserved in LDS).
 template <typename T>
 hipError_t launch_push_class(int cls, const PushArgs<T> &a, int rows_alloc, hipStream_t s);
+// Whether class cls can hold a stream of m regressors and capacity r_max,
+// and the class's shape (rank capacity, column capacity, threads).
+bool class_fits(int cls, int m, int r_max);
+int class_mmax(int cls);
+int class_threads(int cls);
+// Process-wide placement rules (see rg_set_class_rules in rg.h).
+void set_class_rules(const int *m_hi, const int *r_max_hi, const int *cls, int n);
 // The blocked kernel's variants (rg_mf.hip), numbered 0..5.
 int mf_choose(int m, int r_max);
+bool mf_fits(int v, int m, int r_max);
+int mf_mmax(int v);
+int mf_threads(int v);
 int mf_rmax(int v);
 hipError_t mf_prepare(int v, int r_max);
 hipError_t mf_launch(int v, const PushArgs<float> &a, int r_max, hipStream_t s);

@@ -939,6 +939,42 @@ int mf_choose(int m, int r_max) {
     return -1;
 }
 
+bool mf_fits(int v, int m, int r_max) {
+    switch (v) {
+        case 0: return fits_k<F0>(m, r_max);
+        case 1: return fits_k<F1>(m, r_max);
+        case 2: return fits_k<F2>(m, r_max);
+        case 3: return fits_k<F3>(m, r_max);
+        case 4: return fits_k<F4>(m, r_max);
+        case 5: return fits_k<F5>(m, r_max);
+    }
+    return false;
+}
+
+int mf_mmax(int v) {
+    switch (v) {
+        case 0: return F0::MMAX;
+        case 1: return F1::MMAX;
+        case 2: return F2::MMAX;
+        case 3: return F3::MMAX;
+        case 4: return F4::MMAX;
+        case 5: return F5::MMAX;
+    }
+    return 0;
+}
+
+int mf_threads(int v) {
+    switch (v) {
+        case 0: return F0::NT;
+        case 1: return F1::NT;
+        case 2: return F2::NT;
+        case 3: return F3::NT;
+        case 4: return F4::NT;
+        case 5: return F5::NT;
+    }
+    return 0;
+}
+
 int mf_rmax(int v) {
     switch (v) {
         case 0: return F0::RMAX;

@@ -25,6 +25,8 @@
 //      K^T to Ct, Gamma^T to C, a unit diagonal to P^-1 and y to w.
 // Every branch condition is a workgroup-wide value (reduced through LDS), so
 // all waves take the same path and meet the same barriers.
+#include <vector>
+
 #include "rg_classes.h"
 #include "rg_lanes.h"
 
@@ -515,8 +517,53 @@ int class_rmax(int cls) {
     return cls >= 3 ? mf_rmax(cls - 3) : 0;
 }
 
+bool class_fits(int cls, int m, int r_max) {
+    switch (cls) {
+        case 0: return fits<C0>(m, r_max);
+        case 1: return fits<C1>(m, r_max);
+        case 2: return fits<C2>(m, r_max);
+    }
+    return cls >= 3 && cls < RG_NUM_CLASSES && mf_fits(cls - 3, m, r_max);
+}
+
+int class_mmax(int cls) {
+    switch (cls) {
+        case 0: return C0::MMAX;
+        case 1: return C1::MMAX;
+        case 2: return C2::MMAX;
+    }
+    return cls >= 3 ? mf_mmax(cls - 3) : 0;
+}
+
+int class_threads(int cls) {
+    switch (cls) {
+        case 0: return C0::NT;
+        case 1: return C1::NT;
+        case 2: return C2::NT;
+    }
+    return cls >= 3 ? mf_threads(cls - 3) : 0;
+}
+
+namespace {
+struct ClassRule {
+    int m_hi, r_max_hi, cls;
+};
+std::vector<ClassRule> g_rules;  // empty: the built-in order below
+}  // namespace
+
+void set_class_rules(const int *m_hi, const int *r_max_hi, const int *cls, int n) {
+    g_rules.clear();
+    for (int k = 0; k < n; ++k) g_rules.push_back({m_hi[k], r_max_hi[k], cls[k]});
+}
+
 int choose_class(int m, int r_max, int dtype) {
     if (dtype != 0) return -1;  // FP32 state only
+    for (const ClassRule &rule : g_rules) {
+        if (m > rule.m_hi || r_max > rule.r_max_hi) continue;
+        if (rule.cls < 0) return -1;
+        if (class_fits(rule.cls, m, r_max)) return rule.cls;
+    }
+    // built-in: the smallest class that holds the stream
     if (fits<C0>(m, r_max)) return 0;
     if (fits<C1>(m, r_max)) return 1;
     if (fits<C2>(m, r_max)) return 2;

@@ -55,6 +55,10 @@ _SIGS = {
     "rg_batch_get_state": (ctypes.c_int, [_p, _i32, _p, _p, _p, _p]),
     "rg_batch_adjoint": (ctypes.c_int, [_p, _p, _p, _p, _p, _p, _p, _p]),
     "rg_workspace_bytes": (ctypes.c_size_t, [_i32, _p, _p, _i32]),
+    "rg_class_count": (_i32, []),
+    "rg_class_info": (ctypes.c_int, [_i32, _p, _p, _p]),
+    "rg_class_fits": (ctypes.c_int, [_i32, _i32, _i32, _p]),
+    "rg_set_class_rules": (ctypes.c_int, [_p, _p, _p, _i32]),
     "rg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
 }
 
@@ -71,6 +75,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError("librg.so is not built; run `python -m paper_2106_11594_amd.build`")
+        # torch first: librg.so then binds to the HIP runtime torch has loaded, so
+        # the streams and device pointers torch hands over belong to that runtime
+        # (loading librg.so first can bring in a second HIP runtime).
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             f = getattr(L, name)
@@ -328,3 +336,36 @@ def rg_solve(A, Y, eps=None, r_max=None):
     if _RGSolve is None:
         _RGSolve = _autograd_function()
     return _RGSolve.apply(A, Y, eps, r_max)
+
+
+# ---- kernel size classes ------------------------------------------------------
+
+def class_count():
+    """Number of on-chip kernel classes for FP32 streams (rg_class_count)."""
+    return int(lib().rg_class_count())
+
+
+def class_info(cls):
+    """(rank capacity, largest m, threads per stream) of class cls."""
+    r, m, t = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().rg_class_info(int(cls), ctypes.byref(r), ctypes.byref(m), ctypes.byref(t)), "rg_class_info")
+    return r.value, m.value, t.value
+
+
+def class_fits(cls, m, r_max):
+    """Whether class cls can hold a stream with m regressors and capacity r_max."""
+    f = ctypes.c_int32()
+    _check(lib().rg_class_fits(int(cls), int(m), int(r_max), ctypes.byref(f)), "rg_class_fits")
+    return bool(f.value)
+
+
+def set_class_rules(rules):
+    """Install placement rules [(m_hi, r_max_hi, cls), ...] for later handles
+    (rg_set_class_rules); an empty list restores the default placement."""
+    import numpy as np
+    rules = list(rules)
+    a = np.array([r[0] for r in rules] or [0], dtype=np.int32)
+    b = np.array([r[1] for r in rules] or [0], dtype=np.int32)
+    c = np.array([r[2] for r in rules] or [0], dtype=np.int32)
+    _check(lib().rg_set_class_rules(a.ctypes.data_as(ctypes.c_void_p), b.ctypes.data_as(ctypes.c_void_p),
+                                    c.ctypes.data_as(ctypes.c_void_p), len(rules)), "rg_set_class_rules")

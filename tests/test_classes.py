@@ -1,0 +1,53 @@
+"""Kernel size classes and placement rules: the host-side calls (no GPU) and,
+on the GPU, streams forced into larger classes than the default one still
+match the oracle."""
+import numpy as np
+import pytest
+
+from oracle import ref_c
+from paper_2106_11594_amd import workloads as W
+
+
+def test_class_table_is_consistent():
+    from paper_2106_11594_amd import rg
+    n = rg.class_count()
+    assert n >= 2
+    shapes = [rg.class_info(c) for c in range(n)]
+    for c, (rcap, mcap, threads) in enumerate(shapes):
+        assert rcap > 0 and mcap > 0 and threads % 64 == 0
+        assert not rg.class_fits(c, mcap + 1, 1)
+        assert not rg.class_fits(c, mcap, rcap + 1)
+
+
+def test_class_rule_validation():
+    from paper_2106_11594_amd import rg
+    with pytest.raises(RuntimeError):
+        rg.set_class_rules([(64, 12, rg.class_count())])
+    with pytest.raises(RuntimeError):
+        rg.set_class_rules([(64, 12, -2)])
+    with pytest.raises(RuntimeError):
+        rg.class_info(-1)
+    rg.set_class_rules([(64, 12, 0), (256, 128, -1)])
+    rg.set_class_rules([])
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("cls", [3, 5, 8, -1])
+def test_forced_class_matches_oracle(cls):
+    from paper_2106_11594_amd import rg
+    from tests.gpu_util import run_batch
+    bt = W.batched(B=12, m_lo=16, m_hi=60, n_scale=0.3, dtype="f32", seed=5)
+    r_max = np.minimum(bt.ms, bt.rs + 4).astype(np.int32)
+    if cls >= 0:
+        assert all(rg.class_fits(cls, int(m), int(c)) for m, c in zip(bt.ms, r_max))
+    rg.set_class_rules([(1 << 30, 1 << 30, cls)])
+    try:
+        xs, ranks, flags, h = run_batch(bt, "f32", r_max=r_max, eps=1e-3)
+    finally:
+        rg.set_class_rules([])
+    Xo, xoff, ro, st, _ = ref_c.solve_batch(bt.ms, bt.row_ptr, bt.a_off, bt.A, bt.Y, eps=1e-3, caps=r_max)
+    assert (flags == 0).all()
+    for b in range(bt.B):
+        assert ranks[b] == ro[b]
+        xo = Xo[xoff[b]:xoff[b] + bt.ms[b]]
+        assert np.linalg.norm(xs[b] - xo) <= 1e-5 * np.linalg.norm(xo), (cls, b)
