@@ -120,6 +120,18 @@ rg_status upload_order(rg_ctx *h) {
     if (h->dtype == RG_F32)
         for (int f = 1; f < nfam; ++f)
             if (h->fam_count[f] > 0) HIPCHK(rg::prepare_class(f - 1, h->fam_rows[f]));
+    // Forked streams only when two or more class families are active; with one
+    // the family runs on the handle's stream.
+    int nact = 0;
+    for (int f = 1; f < nfam; ++f) nact += h->fam_count[f] > 0;
+    if (nact >= 2) {
+        if (!h->fork && hipEventCreateWithFlags(&h->fork, hipEventDisableTiming) != hipSuccess) return RG_E_DEVICE;
+        for (int f = 1; f < nfam; ++f)
+            if (h->fam_count[f] > 0 && !h->aux[f])
+                if (hipStreamCreateWithFlags(&h->aux[f], hipStreamNonBlocking) != hipSuccess ||
+                    hipEventCreateWithFlags(&h->join[f], hipEventDisableTiming) != hipSuccess)
+                    return RG_E_DEVICE;
+    }
     return RG_OK;
 }
 
@@ -141,9 +153,9 @@ rg_status push_impl(rg_ctx *h, const void *gamma, const void *y, const int64_t *
     HIPCHK(rg::launch_reset_counter(h->d_counter, h->stream));
     // Size-class families run concurrently on forked streams (largest class
     // first), joined back into the handle's stream.
-    const bool serial = (h->opts & RG_OPT_SERIAL_CLASSES) != 0;
     int nact = 0;
     for (int f = 1; f < RG_MAX_FAMILIES; ++f) nact += h->fam_count[f] > 0;
+    const bool serial = (h->opts & RG_OPT_SERIAL_CLASSES) != 0 || nact < 2;
     if (nact > 0 && !serial) HIPCHK(hipEventRecord(h->fork, h->stream));
     for (int f = RG_MAX_FAMILIES - 1; f >= 1; --f) {
         if (h->fam_count[f] == 0) continue;
@@ -309,13 +321,6 @@ rg_status rg_batch_init(rg_handle *out, int32_t B, const int32_t *m, const int32
         hipMemcpyAsync(h->d_meta, h->h_meta.data(), sizeof(StreamMeta) * B, hipMemcpyHostToDevice, h->stream) !=
             hipSuccess)
         st = RG_E_DEVICE;
-    if (st == RG_OK) {
-        if (hipEventCreateWithFlags(&h->fork, hipEventDisableTiming) != hipSuccess) st = RG_E_DEVICE;
-        for (int f = 1; f < RG_MAX_FAMILIES && st == RG_OK; ++f)
-            if (hipStreamCreateWithFlags(&h->aux[f], hipStreamNonBlocking) != hipSuccess ||
-                hipEventCreateWithFlags(&h->join[f], hipEventDisableTiming) != hipSuccess)
-                st = RG_E_DEVICE;
-    }
     h->cost.resize(B);
     for (int b = 0; b < B; ++b) h->cost[b] = (int64_t)h->h_meta[b].m * h->h_meta[b].m * h->h_meta[b].r_max;
     if (st == RG_OK) st = upload_order(h);

@@ -88,8 +88,11 @@ struct MF {
     static constexpr int CH = MMAX / 4;                               // float4 chunks per row
     // X1 (doubles): block-mode scalars and partial sums, or the row-mode vectors
     static constexpr int X1_RR = 0, X1_GW = 16 * NW, X1_GG = 32 * NW, X1_YV = 32 * NW + 16;
-    static constexpr int X1_SP = 32 * NW + 64, X1_L = X1_SP + 1024, X1_C = X1_L + 256, X1_COL = X1_C + 32;
-    static constexpr int X1_DW = X1_COL + 32;
+    // S partials: 4 records of 16 x 16 with row stride 17, so that reading one row per lane is free of bank conflicts
+    static constexpr int SPR = 17, SPS = 16 * SPR;
+    static constexpr int X1_SP = 32 * NW + 64, X1_L = X1_SP + 4 * SPS, X1_C = X1_L + 256, X1_COL = X1_C + 32;
+    static constexpr int CBW = NW == 4 ? 4 : 1;                       // Cholesky panel width (1: column by column)
+    static constexpr int X1_DW = X1_COL + 96;
     static constexpr int X1_GAM = 0, X1_ZETA = RMAX, X1_RED = 2 * RMAX, X1_GR = 2 * RMAX + 4 * NW;
     static constexpr int X1_D = cmax(cmax(KB * MMAX / 2, X1_DW + RMAX), X1_GR + MMAX);
     // X2 (doubles): G (16 x RMAX), then Z and T (RMAX x 16); or the row ring
@@ -430,38 +433,42 @@ __global__ void __launch_bounds__(K::NT) k_push_mf(PushArgs<float> a, int ra) {
             if (NW == 8) {
                 if (wv >= 4) {
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) x1[K::X1_SP + 256 * (wv - 4) + 16 * (4 * v + lg) + li] = sacc[v];
+                    for (int v = 0; v < 4; ++v) x1[K::X1_SP + K::SPS * (wv - 4) + K::SPR * (4 * v + lg) + li] = sacc[v];
                 }
                 __syncthreads();
                 if (wv < 4) {
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) sacc[v] += x1[K::X1_SP + 256 * wv + 16 * (4 * v + lg) + li];
+                    for (int v = 0; v < 4; ++v) sacc[v] += x1[K::X1_SP + K::SPS * wv + K::SPR * (4 * v + lg) + li];
                 }
             }
             if (wv < 4) {
 #pragma unroll
-                for (int v = 0; v < 4; ++v) x1[K::X1_SP + 256 * wv + 16 * (4 * v + lg) + li] = sacc[v];
+                for (int v = 0; v < 4; ++v) x1[K::X1_SP + K::SPS * wv + K::SPR * (4 * v + lg) + li] = sacc[v];
             }
             __syncthreads();
 
             // ---- Cholesky S = L L^T (lane i holds row i), c = L^-1 (y - G w) ----
-            // Wave 0 factors S = L L^T (lane i holds row i).  Step k publishes column
-            // k and the running value of L^-1 (y - G w) through LDS; LDS accesses of
-            // one wave are performed in program order, so the wave needs no barrier.
-            // A pivot that is not positive and finite ends the prefix of applied rows
-            // (ndd); what follows it is computed but never used.
+            // Wave 0 factors S = L L^T (lane i holds row i) in panels of CBW columns:
+            // the panel's columns and the running value of L^-1 (y - G w) are shared
+            // through LDS once per panel (LDS accesses of one wave are performed in
+            // program order, so no barrier is needed), every lane factors the panel
+            // from the shared copy, then updates its own row past the panel.  A pivot
+            // that is not positive and finite ends the prefix of applied rows (ndd);
+            // what follows it is computed but never used.
             if (wv == 0) {
+                constexpr int CBW = K::CBW;
                 double srow[16];
 #pragma unroll
                 for (int cc = 0; cc < 16; ++cc) srow[cc] = cc == li ? 1.0 : 0.0;
 #pragma unroll 1
                 for (int q = 0; q < 4; ++q) {
 #pragma unroll
-                    for (int cc = 0; cc < 16; ++cc) srow[cc] += x1[K::X1_SP + 256 * q + 16 * li + cc];
+                    for (int cc = 0; cc < 16; ++cc) srow[cc] += x1[K::X1_SP + K::SPS * q + K::SPR * li + cc];
                 }
                 double cy = rowok ? dyi : 0.0;
                 double mypiv = 1.0, myc = 0.0, myinv = 0.0;
                 double *col = x1 + K::X1_COL;
+                if constexpr (CBW == 1) {
 #pragma unroll
                 for (int k = 0; k < 16; ++k) {
                     col[li] = srow[k];
@@ -492,6 +499,64 @@ __global__ void __launch_bounds__(K::NT) k_push_mf(PushArgs<float> a, int ra) {
                     if (li > k) cy -= lik * ck;
 #pragma unroll
                     for (int j = k + 1; j < 16; ++j) srow[j] -= lik * ljk[j];
+                }
+                } else {
+#pragma unroll
+                for (int kb = 0; kb < 16; kb += CBW) {
+                    if (lg == 0) {
+#pragma unroll
+                        for (int q = 0; q < CBW; ++q) col[16 * q + li] = srow[kb + q];
+                        col[16 * CBW + li] = cy;
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                    double pc[CBW][16], cyv[CBW];  // pc[q][j] = S[j][kb + q] at the panel start (j >= kb)
+#pragma unroll
+                    for (int q = 0; q < CBW; ++q)
+#pragma unroll
+                        for (int h = kb / 2; h < 8; ++h) {
+                            const double2 v2 = reinterpret_cast<const double2 *>(col + 16 * q)[h];
+                            pc[q][2 * h] = v2.x;
+                            pc[q][2 * h + 1] = v2.y;
+                        }
+#pragma unroll
+                    for (int q = 0; q < CBW; ++q) cyv[q] = col[16 * CBW + kb + q];
+                    __builtin_amdgcn_wave_barrier();  // this panel's loads before the next panel's stores
+                    double lik[CBW];
+#pragma unroll
+                    for (int q = 0; q < CBW; ++q) {
+                        const int k = kb + q;
+                        const double piv = pc[q][k];
+                        const double inv = rsqrt_f64(piv), lkk = piv * inv;
+#pragma unroll
+                        for (int j = k; j < 16; ++j) pc[q][j] *= inv;  // column k of L, rows j >= k
+                        const double ck = cyv[q] * inv;
+                        lik[q] = srow[k] * inv;
+                        if (li == k) {
+                            mypiv = piv;
+                            myc = ck;
+                            myinv = inv;
+                        }
+                        srow[k] = li == k ? lkk : (li > k ? lik[q] : 0.0);
+                        if (li > k) cy -= lik[q] * ck;
+#pragma unroll
+                        for (int q2 = q + 1; q2 < CBW; ++q2) cyv[q2] -= pc[q][kb + q2] * ck;
+#pragma unroll
+                        for (int q2 = q + 1; q2 < CBW; ++q2) {
+                            const int k2 = kb + q2;
+                            const double f = pc[q][k2];  // L[k2][k]
+#pragma unroll
+                            for (int j = k2; j < 16; ++j) pc[q2][j] -= pc[q][j] * f;
+                            srow[k2] -= lik[q] * f;
+                        }
+                    }
+#pragma unroll
+                    for (int j = kb + CBW; j < 16; ++j) {
+                        double acc = srow[j];
+#pragma unroll
+                        for (int q = 0; q < CBW; ++q) acc -= lik[q] * pc[q][j];
+                        srow[j] = acc;
+                    }
+                }
                 }
                 const uint64_t badp = __ballot(!(mypiv > 0.0 && isfinite(mypiv))) & 0xFFFFull;
                 const int nbad = badp ? (int)__builtin_ctzll(badp) : 16;
