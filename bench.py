@@ -27,6 +27,46 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_batched_B4096.md")
+
+
+def kernel_digest():
+    """SHA-256 over the kernel sources and the class placement rules: the
+    counter-based traffic figure is valid only for the build it was taken on."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2106_11594_amd")
+    files = sorted(f for f in os.listdir(os.path.join(d, "csrc")) if f.endswith((".hip", ".h")))
+    hsh = hashlib.sha256()
+    for f in [os.path.join("csrc", f) for f in files] + ["class_rules.json"]:
+        path = os.path.join(d, f)
+        if os.path.exists(path):
+            hsh.update(f.encode())
+            with open(path, "rb") as fh:
+                hsh.update(fh.read())
+    return hsh.hexdigest()
+
+
+def measured_traffic(B):
+    """HBM bytes of one push from the committed counter summary (FETCH_SIZE +
+    WRITE_SIZE of the push kernels, each scaled by the ratio of the known
+    size of a plain copy to what the same counter read for it), or None when
+    the summary is missing or was taken on other kernel sources or another
+    workload.  Counter collection serialises the dispatches, so the figure is
+    the same for concurrent and serial class launches."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        text = f.read()
+    try:
+        blob = text.split("```json", 1)[1].split("```", 1)[0]
+        rec = json.loads(blob)
+    except (IndexError, ValueError):
+        return None
+    if rec.get("kernel_digest") != kernel_digest() or rec.get("streams") != B:
+        return None
+    return float(rec["fetch_kib"]) * 1024 * rec["fetch_scale"] + float(rec["write_kib"]) * 1024 * rec["write_scale"]
+
+
 def headroom(m, r, cap=128):
     """Rank capacity given to each stream: the planted rank plus 4, at most
     128 (the largest capacity the on-chip kernel classes hold)."""
@@ -61,6 +101,9 @@ def main():
     ap.add_argument("--serial-classes", action="store_true", help="launch size classes one after another")
     ap.add_argument("--default-classes", action="store_true",
                     help="ignore the autotuned class rules (paper_2106_11594_amd/class_rules.json)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="after the timed steps, run a plain copy kernel (out = -in) over MIB MiB twice, as the "
+                         "reference point for HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: the batched streams are independent and this build "
@@ -125,8 +168,17 @@ def main():
     flops, byts = model(bt.ms, bt.rs, bt.ns)
     achieved = byts / (push_ms / 1e3) / 1e9
     tflops = flops / (push_ms / 1e3) / 1e12
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+    traffic = None if args.default_classes else measured_traffic(bt.B)
     roof = {"bound": "mfma", "achieved": tflops, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-            "frac": tflops / PEAK_FP64_TFLOPS, "traffic": None,
+            "frac": tflops / PEAK_FP64_TFLOPS, "traffic": traffic,
             "kernel": "k_push_mf (blocked dependent rows on FP64 matrix cores, m > 64 or r_max > 32) and "
                       "k_push_rk (small streams), one launch per size class, concurrent; state on chip",
             "algorithmic_flops_per_launch": flops, "algorithmic_state_bytes_per_launch": byts,
