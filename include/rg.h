@@ -65,9 +65,10 @@ typedef enum { RG_F32 = 0, RG_F64 = 1 } rg_dtype;
 #define RG_OPT_GENERIC_KERNEL 0x2u  /* force the global-memory kernel (testing) */
 #define RG_OPT_SERIAL_CLASSES 0x4u  /* launch the size classes one after another on the
                                        handle's stream instead of on forked streams */
-#define RG_OPT_ROW_BY_ROW     0x8u  /* never apply dependent rows in blocks: every row is
-                                       one call of Algorithm 1 (reference path for the
-                                       blocked variant) */
+#define RG_OPT_ROW_BY_ROW     0x8u  /* never apply rows in blocks: every row is one call of
+                                       Algorithm 1 (reference path for the blocked variant) */
+#define RG_OPT_DEPENDENT_BLOCKS_ONLY 0x10u  /* blocks take dependent rows only; independent
+                                              rows are taken one at a time */
 
 typedef struct {
     int32_t dtype;   /* rg_dtype */

@@ -25,6 +25,7 @@ constexpr uint32_t FLAG_RANK_CAPACITY = 0x2u;
 constexpr uint32_t FLAG_DENOMINATOR = 0x4u;
 constexpr uint32_t OPT_NO_REPROJECT = 0x1u;
 constexpr uint32_t OPT_ROW_BY_ROW = 0x8u;
+constexpr uint32_t OPT_DEPENDENT_BLOCKS_ONLY = 0x10u;
 
 // Arguments of a push launch (by value).
 template <typename T>

@@ -93,6 +93,7 @@ struct MF {
     static constexpr int X1_SP = 32 * NW + 64, X1_L = X1_SP + 4 * SPS, X1_C = X1_L + 256, X1_COL = X1_C + 32;
     static constexpr int CBW = NW == 4 ? 4 : 1;                       // Cholesky panel width (1: column by column)
     static constexpr int X1_DW = X1_COL + 96;
+    static constexpr int X1_M = X1_SP;  // independent block: M, after the records are read
     static constexpr int X1_GAM = 0, X1_ZETA = RMAX, X1_RED = 2 * RMAX, X1_GR = 2 * RMAX + 4 * NW;
     static constexpr int X1_D = cmax(cmax(KB * MMAX / 2, X1_DW + RMAX), X1_GR + MMAX);
     // X2 (doubles): G (16 x RMAX), then Z and T (RMAX x 16); or the row ring
@@ -233,8 +234,9 @@ __global__ void __launch_bounds__(K::NT) k_push_mf(PushArgs<float> a, int ra) {
     };
     const bool reproject = !(a.opts & OPT_NO_REPROJECT);
     const bool use_blocks = !(a.opts & OPT_ROW_BY_ROW);
+    const bool ind_blocks = use_blocks && !(a.opts & OPT_DEPENDENT_BLOCKS_ONLY);
     int64_t i = i0, applied = 0;
-    bool block_mode = false;
+    bool block_mode = ind_blocks;
     bool ring_ok = false;  // row mode: row i is in ring slot cur, pre holds row i + 1
     int cur = 0;
     constexpr int PF = (MMAX + K::NT - 1) / K::NT;
@@ -276,11 +278,13 @@ __global__ void __launch_bounds__(K::NT) k_push_mf(PushArgs<float> a, int ra) {
 
             // ---- G = Gamma_blk Ct^T: tiles u = wv + 4 ups of G^T ----
             const int nur = (r + 15) / 16;
-            d4 gacc[UPW];
+            // G^T tiles of the 16 rows held in x1f (block-row layout) against the Ct
+            // rows 16 u + i of this wave's tiles; returns this lane's part of the
+            // rows' squared norms
+            auto g_loop = [&](d4 (&gacc)[UPW]) -> double {
 #pragma unroll
-            for (int ups = 0; ups < UPW; ++ups) gacc[ups] = (d4){0.0, 0.0, 0.0, 0.0};
-            double gsq = 0.0;
-            {
+                for (int ups = 0; ups < UPW; ++ups) gacc[ups] = (d4){0.0, 0.0, 0.0, 0.0};
+                double gsq = 0.0;
                 // chunk 4q + g of a row with (row & 15) == i sits at physical chunk (4q + g) ^ i;
                 // the operands of chunk q + 1 are loaded while chunk q is multiplied
                 const float *gbase = x1f + li * MMAX;
@@ -318,8 +322,10 @@ __global__ void __launch_bounds__(K::NT) k_push_mf(PushArgs<float> a, int ra) {
                         }
                     }
                 }
-            }
-            gsq = sum_rows(gsq);  // ||Gamma_i||^2
+                return gsq;
+            };
+            d4 gacc[UPW];
+            const double gsq = sum_rows(g_loop(gacc));  // ||Gamma_i||^2
             double gwp = 0.0;     // this wave's part of (G w)_i
 #pragma unroll
             for (int ups = 0; ups < UPW; ++ups) {
@@ -376,12 +382,16 @@ __global__ void __launch_bounds__(K::NT) k_push_mf(PushArgs<float> a, int ra) {
             const double eps = a.eps >= 0.0 ? a.eps : ((double)m * m * r + (double)m * r + (double)m) * 0x1p-52;
             int nd;
             uint32_t stop = 0u;
+            double g2row;  // ||Gamma_i||^2 of block row i
+            bool badrow;   // block row i or its target is not finite
             {
                 double r2 = 0.0;
 #pragma unroll
                 for (int q = 0; q < NW; ++q) r2 += x1[K::X1_RR + 16 * q + li];
                 const double g2 = x1[K::X1_GG + li], yj = x1[K::X1_YV + li];
                 const bool bad = li < nblk && (!isfinite(g2) || !isfinite(yj));
+                g2row = g2;
+                badrow = bad;
                 const double nr = sqrt(r2);
                 const bool indep = li < nblk && !((r2 == 0.0) || (nr < eps) || (nr < eps * sqrt(g2)));
                 const uint64_t fail = __ballot(bad || indep) & 0xFFFFull;
@@ -393,7 +403,7 @@ __global__ void __launch_bounds__(K::NT) k_push_mf(PushArgs<float> a, int ra) {
 #pragma unroll
             for (int q = 0; q < NW; ++q) gwi += x1[K::X1_GW + 16 * q + li];
             const double dyi = yrow - gwi;
-            if (nd == 0) {
+            if (nd == 0 && (stop || !ind_blocks)) {
                 if (stop) {
                     flags |= stop;
                     break;
@@ -402,11 +412,82 @@ __global__ void __launch_bounds__(K::NT) k_push_mf(PushArgs<float> a, int ra) {
                 ring_ok = false;
                 continue;
             }
-
-            // ---- Z = P^-1 G^T and this wave's part of S = I + G Z ----
+            // nd == 0: row i is independent and starts a block of independent rows
+            const bool indblk = nd == 0;
+            const int r0 = r, nst = min(nblk, rmax - r0);  // rows that fit below the rank capacity
+            if (indblk && r0 == rmax) {
+                flags |= FLAG_RANK_CAPACITY;
+                break;
+            }
             const bool rowok = li < nd;
             d4 z[UPW];
             d4 sacc = (d4){0.0, 0.0, 0.0, 0.0};
+            if (indblk) {
+                // ---- independent rows: R (twice projected) and R R^T ----
+                // R = Gamma_blk - G C with the rows read again from global memory and G
+                // from X2; stored in FP32 to x1f (block-row layout) or to Ct rows r0 + i
+                // (i < nst), which are zero and become the new rows; with gram, this
+                // wave's part of R R^T is accumulated into sacc (result layout)
+                auto r_pass = [&](bool to_ct, bool gram) {
+#pragma unroll
+                    for (int tau = 0; tau < TPW; ++tau) {
+                        const int ct = wv + NW * tau;
+                        if (ct < nq) {
+                            d4 d;
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) {
+                                const int col = 16 * ct + 4 * v + lg;
+                                d[v] = (li < nblk && col < m) ? (double)G0[(i - i0 + li) * (int64_t)m + col] : 0.0;
+                            }
+#pragma unroll
+                            for (int u2 = 0; u2 < NU; ++u2) {
+                                if (u2 < nur) {
+#pragma unroll
+                                    for (int v = 0; v < 4; ++v) {
+                                        const int s = 4 * u2 + v;
+                                        d = mma(cval(s, tau), -x2[gpos<RMAX>(li, 4 * s + lg)], d);
+                                    }
+                                }
+                            }
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) {
+                                const int c4 = 4 * ct + v;
+                                if (!to_ct) {
+                                    x1f[li * MMAX + 4 * (c4 ^ li) + lg] = (float)d[v];
+                                } else if (li < nst) {
+                                    const int k = r0 + li;
+                                    sct[(size_t)k * MMAX + 4 * (c4 ^ (k & 15)) + lg] = (float)d[v];
+                                }
+                            }
+                            if (gram) {
+#pragma unroll
+                                for (int v = 0; v < 4; ++v) sacc = mma(d[v], d[v], sacc);
+                            }
+                        }
+                    }
+                };
+#pragma unroll
+                for (int ups = 0; ups < UPW; ++ups) z[ups] = (d4){0.0, 0.0, 0.0, 0.0};
+                __syncthreads();  // the rank test's reads of X1 are done
+                if (reproject && r0 > 0) {
+                    // second projection ("twice is enough"): G += R1 Ct^T
+                    r_pass(false, false);
+                    __syncthreads();
+                    d4 g2acc[UPW];
+                    (void)g_loop(g2acc);
+#pragma unroll
+                    for (int ups = 0; ups < UPW; ++ups) {
+                        const int u = wv + NW * ups;
+                        if (u < nur) {
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) x2[gpos<RMAX>(li, 16 * u + 4 * v + lg)] += g2acc[ups][v];
+                        }
+                    }
+                    __syncthreads();
+                }
+                r_pass(true, true);
+            } else {
+            // ---- Z = P^-1 G^T and this wave's part of S = I + G Z ----
 #pragma unroll
             for (int ups = 0; ups < UPW; ++ups) {
                 const int u = wv + NW * ups;
@@ -429,7 +510,8 @@ __global__ void __launch_bounds__(K::NT) k_push_mf(PushArgs<float> a, int ra) {
                     }
                 }
             }
-            // four records of partial sums of S; with 8 waves the upper half folds in first
+            }
+            // four records of partial sums of S (or R R^T); with 8 waves the upper half folds in first
             if (NW == 8) {
                 if (wv >= 4) {
 #pragma unroll
@@ -459,7 +541,7 @@ __global__ void __launch_bounds__(K::NT) k_push_mf(PushArgs<float> a, int ra) {
                 constexpr int CBW = K::CBW;
                 double srow[16];
 #pragma unroll
-                for (int cc = 0; cc < 16; ++cc) srow[cc] = cc == li ? 1.0 : 0.0;
+                for (int cc = 0; cc < 16; ++cc) srow[cc] = (cc == li && !indblk) ? 1.0 : 0.0;
 #pragma unroll 1
                 for (int q = 0; q < 4; ++q) {
 #pragma unroll
@@ -558,6 +640,7 @@ __global__ void __launch_bounds__(K::NT) k_push_mf(PushArgs<float> a, int ra) {
                     }
                 }
                 }
+                if (!indblk) {
                 const uint64_t badp = __ballot(!(mypiv > 0.0 && isfinite(mypiv))) & 0xFFFFull;
                 const int nbad = badp ? (int)__builtin_ctzll(badp) : 16;
                 const int nk = nbad < nd ? nbad : nd;
@@ -568,17 +651,169 @@ __global__ void __launch_bounds__(K::NT) k_push_mf(PushArgs<float> a, int ra) {
                     x1[K::X1_C + 16 + li] = li < nk ? myinv : 0.0;
                 }
                 if (li == 0 && lg == 0) x1[K::X1_COL] = (double)nk;
+                } else {
+                    // Pivot j of R R^T is the squared norm of row j's rejection against
+                    // the span of C and of the block rows before it: the sequential rank
+                    // test of Section 3 for every row at once.  ni = the longest prefix of
+                    // finite rows that pass it and fit below the rank capacity.
+                    const double epsl = a.eps >= 0.0 ? a.eps
+                                                     : ((double)m * m * (r0 + li) + (double)m * (r0 + li) + (double)m) * 0x1p-52;
+                    const double nrm = sqrt(mypiv);
+                    const bool ok = li < nst && !badrow && mypiv > 0.0 && isfinite(mypiv) && !(nrm < epsl) &&
+                                    !(nrm < epsl * sqrt(g2row));
+                    const uint64_t failm = __ballot(!ok) & 0xFFFFull;
+                    const uint64_t badm = __ballot(li < nblk && badrow) & 0xFFFFull;
+                    const int ni = failm ? (int)__builtin_ctzll(failm) : 16;
+                    if (lg == 0) {
+#pragma unroll
+                        for (int k = 0; k < 16; ++k) x1[K::X1_L + 16 * li + k] = srow[k];
+                        x1[K::X1_C + 16 + li] = myinv;
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                    // column i of W = L^-1 on the first ni rows (zero elsewhere)
+                    double wc[16];
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) {
+                        double a0 = li == j ? 1.0 : 0.0, a1 = 0.0;
+                        const double2 *lrow = reinterpret_cast<const double2 *>(x1 + K::X1_L + 16 * j);
+#pragma unroll
+                        for (int j2 = 0; j2 < j; j2 += 2) {
+                            const double2 l2 = lrow[j2 / 2];
+                            a0 -= wc[j2] * l2.x;
+                            if (j2 + 1 < j) a1 -= wc[j2 + 1] * l2.y;
+                        }
+                        wc[j] = j < ni ? (a0 + a1) * x1[K::X1_C + 16 + j] : 0.0;
+                    }
+                    // M = W^T W = (R R^T)^-1 on the first ni rows, in the result layout
+                    d4 macc = (d4){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int ks = 0; ks < 4; ++ks) {
+                        const double av = lg == 0 ? wc[4 * ks] : lg == 1 ? wc[4 * ks + 1] : lg == 2 ? wc[4 * ks + 2] : wc[4 * ks + 3];
+                        macc = mma(av, av, macc);
+                    }
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) x1[K::X1_M + 16 * (4 * v + lg) + li] = macc[v];
+                    if (li == 0 && lg == 0) {
+                        x1[K::X1_COL] = (double)ni;
+                        x1[K::X1_COL + 1] = ((badm >> ni) & 1ull) ? 1.0 : 0.0;
+                    }
+                }
             }
             // Z to LDS for the substitution (every read of G ended at the barrier above)
+            if (!indblk) {
 #pragma unroll
-            for (int ups = 0; ups < UPW; ++ups) {
-                const int u = wv + NW * ups;
-                if (u < nur) {
+                for (int ups = 0; ups < UPW; ++ups) {
+                    const int u = wv + NW * ups;
+                    if (u < nur) {
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) x2[zpos(16 * u + 4 * v + lg, li)] = z[ups][v];
+                        for (int v = 0; v < 4; ++v) x2[zpos(16 * u + 4 * v + lg, li)] = z[ups][v];
+                    }
                 }
             }
             __syncthreads();
+            if (indblk) {
+                // ---- independent rows 0 .. ni-1 of the block: K = M R, Ct -= G^T K ----
+                const int ni = (int)x1[K::X1_COL];
+                const bool nonf = x1[K::X1_COL + 1] != 0.0;
+                if (ni == 0) {
+                    // the first row failed the test on its twice-projected rejection: clear
+                    // the rows of Ct that held R and take the row alone
+                    for (int idx = t; idx < nst * CH; idx += K::NT) {
+                        const int k = r0 + idx / CH, cc = idx % CH;
+                        *reinterpret_cast<float4 *>(sct + (size_t)k * MMAX + 4 * cc) = make_float4(0.f, 0.f, 0.f, 0.f);
+                    }
+                    block_mode = false;
+                    ring_ok = false;
+                    continue;
+                }
+                const int nur0 = nur;
+#pragma unroll
+                for (int tau = 0; tau < TPW; ++tau) {
+                    const int ct = wv + NW * tau;
+                    if (ct < nq) {
+                        // column 16 ct + i: float4 chunk cq, element ce
+                        const int cq = 4 * ct + (li >> 2), ce = li & 3;
+                        // K[4v + g][16 ct + i] = sum_j M[4v + g][j] R[j][16 ct + i]; each lane
+                        // reads and then rewrites the same four elements of rows r0 + 4 ks + g
+                        double bk[4];
+#pragma unroll
+                        for (int ks = 0; ks < 4; ++ks) {
+                            const int j = 4 * ks + lg, k = r0 + j;
+                            bk[ks] = j < ni ? (double)sct[(size_t)k * MMAX + 4 * (cq ^ (k & 15)) + ce] : 0.0;
+                        }
+                        d4 kt = (d4){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                        for (int ks = 0; ks < 4; ++ks) kt = mma(x1[K::X1_M + 16 * (4 * ks + lg) + li], bk[ks], kt);
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int j = 4 * v + lg, k = r0 + j;
+                            if (j >= ni) kt[v] = 0.0;
+                            if (j < nst) sct[(size_t)k * MMAX + 4 * (cq ^ (k & 15)) + ce] = (float)kt[v];
+                        }
+                        // Ct[k][16 ct + i] -= sum_j G[j][k] K[j][16 ct + i] for k < r0; kt[ks]
+                        // is the B operand K[4 ks + g][16 ct + i]
+#pragma unroll 1
+                        for (int u = 0; u < nur0; ++u) {
+                            d4 acc;
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) {
+                                const int k = 16 * u + 4 * v + lg;
+                                acc[v] = k < r0 ? (double)sct[(size_t)k * MMAX + 4 * (cq ^ (k & 15)) + ce] : 0.0;
+                            }
+#pragma unroll
+                            for (int ks = 0; ks < 4; ++ks) {
+                                const int j = 4 * ks + lg;
+                                const double ga = j < ni ? x2[gpos<RMAX>(j, 16 * u + li)] : 0.0;
+                                acc = mma(-ga, kt[ks], acc);
+                            }
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) {
+                                const int k = 16 * u + 4 * v + lg;
+                                if (k < r0) sct[(size_t)k * MMAX + 4 * (cq ^ (k & 15)) + ce] = (float)acc[v];
+                            }
+                        }
+                    }
+                }
+                // appends: rows r0 .. r0 + ni - 1 of C (the raw rows), P^-1 = 1 on the
+                // diagonal, w = y (Theorem 4 in coordinates)
+#pragma unroll
+                for (int ups = 0; ups < UPW; ++ups) {
+                    const int u = wv + NW * ups;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int kk = 16 * u + 4 * v + lg;
+                        if (kk >= r0 && kk < r0 + ni) wr[ups][v] = (double)a.y[i + (kk - r0)];
+#pragma unroll
+                        for (int u2 = 0; u2 < NU; ++u2) {
+                            const int row = 16 * u2 + 4 * v + lg, colp = 16 * u + li;
+                            if (row == colp && row >= r0 && row < r0 + ni) p[u2][ups][v] = 1.0;
+                        }
+                    }
+                }
+                if constexpr (K::CG) {
+                    for (int idx = t; idx < ni * m; idx += K::NT) {
+                        const int j = idx / m, col = idx - j * m;
+                        Cg[(size_t)(r0 + j) * ldm + col] = G0[(i - i0 + j) * (int64_t)m + col];
+                    }
+                } else {
+#pragma unroll
+                    for (int s = 0; s < 4 * NU; ++s)
+#pragma unroll
+                        for (int tau = 0; tau < TPW; ++tau) {
+                            const int row = 4 * s + lg, col = 16 * (wv + NW * tau) + li;
+                            if (row >= r0 && row < r0 + ni && wv + NW * tau < NTT)
+                                c[s][tau] = col < m ? G0[(i - i0 + row - r0) * (int64_t)m + col] : 0.0f;
+                        }
+                }
+                r = r0 + ni;
+                i += ni;
+                applied += ni;
+                if (nonf && ni < nblk) {
+                    flags |= FLAG_NONFINITE;
+                    break;
+                }
+                continue;
+            }
             const int ndd = (int)x1[K::X1_COL];
 
             // ---- T = Z L^-T (row kk per thread, in place) and dw = T c ----
@@ -897,6 +1132,7 @@ __global__ void __launch_bounds__(K::NT) k_push_mf(PushArgs<float> a, int ra) {
                 }
             }
             r += 1;
+            block_mode = ind_blocks;
             __syncthreads();
         }
         ++i;

@@ -1,8 +1,11 @@
-"""The blocked variant (dependent rows applied 16 at a time on the matrix
-cores) against the row-by-row path (RG_OPT_ROW_BY_ROW) and the oracle, on
-stream shapes that use the blocked kernel's variants, including the rows
-where a block has to stop: an independent row inside a block, a non-finite
-row, the rank capacity, zero rows and ragged tails."""
+"""The blocked variant (rows applied up to 16 at a time on the matrix cores:
+runs of dependent rows as one Woodbury update, runs of independent rows as
+one block append) against the dependent-blocks-only path
+(RG_OPT_DEPENDENT_BLOCKS_ONLY), the row-by-row path (RG_OPT_ROW_BY_ROW) and
+the oracle, on stream shapes that use the blocked kernel's variants,
+including the rows where a block has to stop: a row of the other kind inside
+a block, a non-finite row, the rank capacity, zero rows, rows just on either
+side of the rank threshold and ragged tails."""
 import numpy as np
 import pytest
 
@@ -56,14 +59,16 @@ def test_variant_blocked_vs_row_by_row_and_oracle(m, r_max):
     Y, _ = W.targets(rng, A)
     A, Y = _f32(A), _f32(Y)
     xb, rb, fb = _solve(A, Y, r_max)
+    xd, rd, fd = _solve(A, Y, r_max, flags=rg.OPT_DEPENDENT_BLOCKS_ONLY)
     xr, rr, fr = _solve(A, Y, r_max, flags=rg.OPT_ROW_BY_ROW)
     xo, ro, Co, *_ = ref_c.solve(A, Y, eps=1e-3, cap=r_max)
     tol, kap = _kappa_tol(Co)
-    print("m=%d r_max=%d: rank %d/%d/%d, kappa %.3g, blocked %.2e, row-by-row %.2e, between %.2e"
-          % (m, r_max, rb, rr, ro, kap, _rel(xb, xo), _rel(xr, xo), _rel(xb, xr)), flush=True)
-    assert fb == fr == 0
-    assert rb == rr == ro == r
-    assert _rel(xb, xo) <= tol and _rel(xr, xo) <= tol
+    print("m=%d r_max=%d: rank %d/%d/%d/%d, kappa %.3g, blocked %.2e, dependent blocks only %.2e, row-by-row %.2e, "
+          "blocked vs row-by-row %.2e" % (m, r_max, rb, rd, rr, ro, kap, _rel(xb, xo), _rel(xd, xo), _rel(xr, xo),
+                                          _rel(xb, xr)), flush=True)
+    assert fb == fd == fr == 0
+    assert rb == rd == rr == ro == r
+    assert _rel(xb, xo) <= tol and _rel(xd, xo) <= tol and _rel(xr, xo) <= tol
     assert _rel(xb, xr) <= tol
 
 
@@ -133,3 +138,88 @@ def test_zero_rows_and_incremental_pushes():
     xo, ro, *_ = ref_c.solve(A, Y, eps=1e-3, cap=40)
     assert f1 == f2 == 0 and r1 == r2 == ro == 30
     assert _rel(x1, xo) <= 1e-5 and _rel(x2, xo) <= 1e-5
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("m,r_max", [(120, 50), (200, 100)])
+def test_nonfinite_row_among_independent_rows(m, r_max):
+    """A NaN inside the run of independent rows: the block append stops before
+    it, the rows before it are applied, the stream is flagged."""
+    rng = np.random.default_rng(m + 21)
+    A = W.lowrank_rows(rng, m, r_max - 4, 2 * m)
+    Y, _ = W.targets(rng, A)
+    A, Y = _f32(A).copy(), _f32(Y)
+    A[21, 5] = np.nan  # inside the second block of independent rows
+    x, r, f = _solve(A, Y, r_max)
+    xo, ro, *_ = ref_c.solve(A[:21], Y[:21], eps=1e-3, cap=r_max)
+    assert f == 0x1 and r == ro == 21
+    assert _rel(x, xo) <= 1e-5
+
+
+@pytest.mark.gpu
+def test_zero_and_repeated_rows_among_independent_rows():
+    """Zero rows and exact copies inside the run of independent rows end the
+    block append; the dependent rows between runs go through the Woodbury
+    blocks; the rank and solution follow the oracle."""
+    rng = np.random.default_rng(31)
+    A = W.lowrank_rows(rng, 180, 60, 300)
+    Y, _ = W.targets(rng, A)
+    A, Y = _f32(A).copy(), _f32(Y).copy()
+    A[5:9] = 0.0
+    Y[5:9] = 0.0
+    A[20] = A[3]
+    A[33] = A[17]
+    x, r, f = _solve(A, Y, 64)
+    xr, rr, fr = _solve(A, Y, 64, flags=0x8)
+    xo, ro, Co, *_ = ref_c.solve(A, Y, eps=1e-3, cap=64)
+    tol, _ = _kappa_tol(Co)
+    assert f == fr == 0 and r == rr == ro == 60
+    assert _rel(x, xo) <= tol and _rel(xr, xo) <= tol
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("delta,indep", [(1e-2, True), (1e-5, False)])
+def test_rows_either_side_of_the_rank_threshold(delta, indep):
+    """Early rows that are a combination of earlier rows plus a perturbation of
+    relative size delta: 1e-2 is independent and 1e-5 dependent at eps 1e-3,
+    wherever the row falls in a block."""
+    rng = np.random.default_rng(41)
+    m, r0 = 150, 40
+    A = W.lowrank_rows(rng, m, r0, 200)
+    A = A.copy()
+    for k in (7, 18, 30):  # inside the first, second and third blocks
+        comb = A[k - 3] - 0.5 * A[k - 5]
+        e = rng.standard_normal(m)
+        A[k] = comb + delta * np.linalg.norm(comb) * e / np.linalg.norm(e)
+    Y, _ = W.targets(rng, A)
+    A, Y = _f32(A), _f32(Y)
+    from paper_2106_11594_amd import rg
+    x, r, f = _solve(A, Y, 64)
+    xr, rr, fr = _solve(A, Y, 64, flags=rg.OPT_ROW_BY_ROW)
+    xo, ro, Co, *_ = ref_c.solve(A, Y, eps=1e-3, cap=64)
+    kap = float(np.linalg.cond(Co))
+    print("delta %.0e: rank %d/%d/%d, kappa %.3g, blocked %.2e, row-by-row %.2e"
+          % (delta, r, rr, ro, kap, _rel(x, xo), _rel(xr, xo)), flush=True)
+    assert f == fr == 0 and r == rr == ro
+    assert (r > r0) == indep
+    # Rows 1e-2 from the span of the earlier ones raise kappa(C) to a few hundred;
+    # the FP32 state then carries the first-order error kappa 2^-23 (row by row
+    # it reaches about 2 kappa 2^-23, the block append about kappa 2^-24).
+    assert _rel(x, xo) <= max(1e-5, kap * 2.0 ** -23)
+    assert _rel(x, xo) <= 2.0 * _rel(xr, xo) + 1e-6
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("m,cap", [(100, 37), (250, 120)])
+def test_rank_fills_the_capacity_exactly(m, cap):
+    """The planted rank equals the capacity: the last block append ends exactly
+    at r_max and no flag is raised; the later (dependent) rows apply."""
+    rng = np.random.default_rng(m + cap)
+    A = W.lowrank_rows(rng, m, cap, cap + 90)
+    Y, _ = W.targets(rng, A)
+    A, Y = _f32(A), _f32(Y)
+    x, r, f = _solve(A, Y, cap)
+    xo, ro, Co, *_ = ref_c.solve(A, Y, eps=1e-3, cap=cap)
+    tol, _ = _kappa_tol(Co)
+    assert f == 0 and r == ro == cap
+    assert _rel(x, xo) <= tol
