@@ -91,7 +91,11 @@ struct MF {
     // S partials: 4 records of 16 x 16 with row stride 17, so that reading one row per lane is free of bank conflicts
     static constexpr int SPR = 17, SPS = 16 * SPR;
     static constexpr int X1_SP = 32 * NW + 64, X1_L = X1_SP + 4 * SPS, X1_C = X1_L + 256, X1_COL = X1_C + 32;
-    static constexpr int CBW = NW == 4 ? 4 : 1;                       // Cholesky panel width (1: column by column)
+    // Waves per SIMD the register allocation is held to: two for the 4-wave
+    // variants whose LDS footprint lets two workgroups share a CU (m <= 192),
+    // which then factor column by column (a panel's registers would not fit)
+    static constexpr int OCC = (NW == 4 && MMAX <= 192) ? 2 : 1;
+    static constexpr int CBW = (NW == 4 && OCC == 1) ? 4 : 1;         // Cholesky panel width (1: column by column)
     static constexpr int X1_DW = X1_COL + 96;
     static constexpr int X1_M = X1_SP;  // independent block: M, after the records are read
     static constexpr int X1_GAM = 0, X1_ZETA = RMAX, X1_RED = 2 * RMAX, X1_GR = 2 * RMAX + 4 * NW;
@@ -131,7 +135,7 @@ __device__ inline void block_sum4(double &a, double &b, double &c, double &d, do
 }
 
 template <class K>
-__global__ void __launch_bounds__(K::NT) k_push_mf(PushArgs<float> a, int ra) {
+__global__ void __launch_bounds__(K::NT, K::OCC) k_push_mf(PushArgs<float> a, int ra) {
     constexpr int RMAX = K::RMAX, MMAX = K::MMAX, NU = K::NU, UPW = K::UPW, TPW = K::TPW;
     constexpr int NB = K::NB, KB = K::KB, CH = K::CH, NW = K::NW, NTT = K::NTT, RS = K::RS;
     extern __shared__ double smem[];
