@@ -357,6 +357,46 @@ __global__ void __launch_bounds__(K::NT, K::OCC) k_push_mf(PushArgs<float> a, in
             for (int tau = 0; tau < TPW; ++tau) {
                 if (wv + NW * tau < nq) {
                     d4 d = (d4){gi[tau][0], gi[tau][1], gi[tau][2], gi[tau][3]};
+                    if constexpr (K::CG) {
+                        // C from global memory: the loads of row tile u2 + 3 are issued
+                        // while the products of row tile u2 run
+                        const int col = 16 * (wv + NW * tau) + li;
+                        const float *cb = Cg + (col < m ? col : 0);
+                        const int rlim = col < m ? r : 0;
+                        float b0[4], b1[4], b2[4];
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int row = 4 * v + lg;
+                            b0[v] = row < rlim ? cb[(size_t)row * ldm] : 0.0f;
+                            b1[v] = row + 16 < rlim ? cb[(size_t)(row + 16) * ldm] : 0.0f;
+                            b2[v] = row + 32 < rlim ? cb[(size_t)(row + 32) * ldm] : 0.0f;
+                        }
+#pragma unroll 1
+                        for (int u2 = 0; u2 < nur; u2 += 3) {
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) {
+                                const int row = 16 * u2 + 4 * v + lg;
+                                d = mma((double)b0[v], -x2[gpos<RMAX>(li, row)], d);
+                                b0[v] = row + 48 < rlim ? cb[(size_t)(row + 48) * ldm] : 0.0f;
+                            }
+                            if (u2 + 1 < nur) {
+#pragma unroll
+                                for (int v = 0; v < 4; ++v) {
+                                    const int row = 16 * u2 + 16 + 4 * v + lg;
+                                    d = mma((double)b1[v], -x2[gpos<RMAX>(li, row)], d);
+                                    b1[v] = row + 48 < rlim ? cb[(size_t)(row + 48) * ldm] : 0.0f;
+                                }
+                            }
+                            if (u2 + 2 < nur) {
+#pragma unroll
+                                for (int v = 0; v < 4; ++v) {
+                                    const int row = 16 * u2 + 32 + 4 * v + lg;
+                                    d = mma((double)b2[v], -x2[gpos<RMAX>(li, row)], d);
+                                    b2[v] = row + 48 < rlim ? cb[(size_t)(row + 48) * ldm] : 0.0f;
+                                }
+                            }
+                        }
+                    } else {
 #pragma unroll
                     for (int u2 = 0; u2 < NU; ++u2) {
                         if (u2 < nur) {
@@ -366,6 +406,7 @@ __global__ void __launch_bounds__(K::NT, K::OCC) k_push_mf(PushArgs<float> a, in
                                 d = mma(cval(s, tau), -x2[gpos<RMAX>(li, 4 * s + lg)], d);
                             }
                         }
+                    }
                     }
                     rsq += d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + d[3] * d[3];
                 }
