@@ -91,6 +91,57 @@ def model(ms, rs, ns, s=4, s_in=4):
     return float(flops.sum()), float(byts.sum())
 
 
+def adjoint_leg(torch, rg, W, steps, warmup):
+    """Differentiable workload (B = 1024 problems, n = 512 rows, m = 128, planted
+    rank 32, FP32): forward = reset + push + solution, backward = the adjoint
+    kernel for L = 1/2 ||x - x_target||^2, each timed with HIP events on the
+    handle's stream.  The backward reads A and Y once, writes dA and dY once and
+    reads each problem's state (C, Ct, P^-1) once: its algorithmic bytes."""
+    bt = W.grad_batch(store=np.float32)
+    dev = torch.device("cuda:0")
+    B, n, m, cap = bt.B, 512, 128, 36
+    A = torch.from_numpy(bt.A).to(dev)
+    Y = torch.from_numpy(bt.Y).to(dev)
+    rp = torch.from_numpy(bt.row_ptr).to(dev)
+    ao = torch.from_numpy(bt.a_off).to(dev)
+    xt = torch.from_numpy(bt.extra["x_target"].astype(np.float32).reshape(-1)).to(dev)
+    h = rg.Batch(bt.ms, r_max=np.full(B, cap, np.int32), dtype="f32", eps=1e-3)
+    h.plan(bt.ns)
+    x = torch.empty(h.n_x, dtype=torch.float32, device=dev)
+    dA = torch.empty_like(A)
+    dY = torch.empty_like(Y)
+    stream = torch.cuda.current_stream()
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    fw, bw = [], []
+    for k in range(warmup + steps):
+        e0, e1, e2 = ev(), ev(), ev()
+        e0.record(stream)
+        h.reset()
+        h.push(A, Y, rp, ao)
+        h.solution(x)
+        e1.record(stream)
+        h.adjoint(A, Y, rp, ao, x - xt, dA, dY)
+        e2.record(stream)
+        torch.cuda.synchronize()
+        if k >= warmup:
+            fw.append(e0.elapsed_time(e1))
+            bw.append(e1.elapsed_time(e2))
+    ranks = h.rank()
+    r = np.minimum(ranks, cap).astype(np.float64)
+    state = float((r * m * 4 * 2 + r * r * 8).sum())
+    bytes_bw = 2.0 * (A.numel() + Y.numel()) * 4 + state
+    f_ms, b_ms = float(np.mean(fw)), float(np.mean(bw))
+    h.close()
+    return {"workload": "differentiable batched solve: B=1024, n=512, m=128, planted rank 32, FP32, "
+                        "L = 1/2 ||x - x_target||^2",
+            "forward_ms": f_ms, "backward_ms": b_ms,
+            "forward_row_updates_per_s": B * n / (f_ms * 1e-3),
+            "ranks_equal_32": int((ranks == 32).sum()), "problems": B,
+            "backward_roofline": {"bound": "hbm", "achieved": bytes_bw / (b_ms * 1e-3) / 1e9, "peak": PEAK_HBM_GBS,
+                                  "unit": "GB/s", "frac": bytes_bw / (b_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                                  "algorithmic_bytes": bytes_bw}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +152,7 @@ def main():
     ap.add_argument("--serial-classes", action="store_true", help="launch size classes one after another")
     ap.add_argument("--default-classes", action="store_true",
                     help="ignore the autotuned class rules (paper_2106_11594_amd/class_rules.json)")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiable-solve (backward) leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the timed steps, run a plain copy kernel (out = -in) over MIB MiB twice, as the "
                          "reference point for HBM byte counters")
@@ -192,6 +244,12 @@ def main():
                       "streams": bt.B, "rows": rows,
                       "class_placement": ("autotuned rules (%d)" % len(rules)) if rules else "default"},
            "roofline": roof}
+
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_leg(torch, rg, W, steps=5, warmup=1)
+        print("adjoint leg: forward %.3f ms, backward %.3f ms" % (out["adjoint"]["forward_ms"],
+                                                                  out["adjoint"]["backward_ms"]),
+              file=sys.stderr, flush=True)
 
     if not args.no_cpu:
         from oracle import ref_c

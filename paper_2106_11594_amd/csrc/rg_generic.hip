@@ -16,6 +16,7 @@
 // Ct C^T = I), which removes the pass over Ct that forms the dependent-case
 // gain K = Ct^T zeta / d; x is formed on demand by the solution kernel.
 #include "rg_internal.h"
+#include "rg_lanes.h"
 
 namespace rg {
 namespace {
@@ -322,22 +323,33 @@ __global__ void __launch_bounds__(NT) k_adjoint(const StreamMeta *meta, const T 
     const int64_t i0 = row_ptr[b], i1 = row_ptr[b + 1];
     const T *Ab = A + a_off[b];
     T *dAb = dA + a_off[b];
-    for (int64_t i = i0 + wid; i < i1; i += NW) {
+    // 16 lanes per row, four rows per wave at a time, so that many rows' loads
+    // are in flight; the row sums are 16-lane DPP reductions
+    const int q = lane & 15, grp = lane >> 4;
+    for (int64_t ib = i0 + 4 * wid; ib < i1; ib += 4 * NW) {  // wave-uniform
+        const int64_t i = ib + grp;
+        const bool ok = i < i1;
         const T *row = Ab + (i - i0) * (int64_t)m;
         double ca = 0.0, cb = 0.0, cx = 0.0;
-        for (int j = lane; j < m; j += 64) {
-            const double v = (double)row[j];
-            ca += v * ss[j];
-            cb += v * st[j];
-            cx += v * sx[j];
+        if (ok) {
+#pragma unroll 8
+            for (int j = q; j < m; j += 16) {
+                const double v = (double)row[j];
+                ca += v * ss[j];
+                cb += v * st[j];
+                cx += v * sx[j];
+            }
         }
-        ca = wave_sum(ca);
-        cb = wave_sum(cb);
-        cx = wave_sum(cx);
-        const double rho = (double)Y[i] - cx;
-        T *drow = dAb + (i - i0) * (int64_t)m;
-        for (int j = lane; j < m; j += 64) drow[j] = (T)(-ca * sx[j] + rho * ss[j] + cb * sp[j]);
-        if (lane == 0) dY[i] = (T)ca;
+        ca = sum16(ca);
+        cb = sum16(cb);
+        cx = sum16(cx);
+        if (ok) {
+            const double rho = (double)Y[i] - cx;
+            T *drow = dAb + (i - i0) * (int64_t)m;
+#pragma unroll 8
+            for (int j = q; j < m; j += 16) drow[j] = (T)(-ca * sx[j] + rho * ss[j] + cb * sp[j]);
+            if (q == 0) dY[i] = (T)ca;
+        }
     }
 }
 
