@@ -17,7 +17,10 @@ raw observations), Ct (C tilde, the dual basis (C C^T)^-1 C, r x m), Pinv
 Pins (all in tests/test_oracle_*.py): the Fraction run equals the independent
 exact solver ``lstsq_exact`` bit for bit; hand-derived worked examples; the
 Penrose equations on the pseudoinverse rebuilt by Theorem 1; truncated-SVD
-solutions; closed forms for a single row, A = I and full column rank.
+solutions; closed forms for a single row, A = I and full column rank.  The
+orthogonal rank factorization variants of Section 2.2 (``variant=``) are
+pinned in tests/test_oracle_variants.py: exactly against the same solver and
+factor invariants for alpha = 1, in FP64 for the orthonormal one.
 """
 from fractions import Fraction
 import math
@@ -38,9 +41,12 @@ class RGState:
     Gamma_r = Gamma).
     """
 
-    def __init__(self, m, zero):
+    def __init__(self, m, zero, variant="base"):
+        if variant not in ("base", "orthogonal", "orthonormal"):
+            raise ValueError(variant)
         self.m = m
         self.zero = zero
+        self.variant = variant
         self.X = [zero] * m
         self.C = []      # list of rows (length m)
         self.Ct = []     # list of rows (length m)
@@ -89,6 +95,14 @@ def update_least_squares(st, Gamma, y, eps):
     C and Ct unchanged).
     Both: X <- X + K (y - Gamma^T X), with the X from before this row.
     Returns True when the row was independent.
+
+    Orthogonal rank factorization (Section 2.2): the
+    independent case stores a rescaled rejection alpha Gamma_r in C instead of
+    Gamma, appends Gamma_r / (alpha ||Gamma_r||^2) to Ct without touching its
+    other rows, and borders Pinv with -alpha zeta and alpha^2 (1 + gamma^T zeta),
+    zeta = Pinv gamma.  alpha = 1 ("orthogonal", rational) or
+    alpha = 1 / ||Gamma_r|| ("orthonormal": C has orthonormal rows, Ct = C).
+    The X update (Theorem 4) and the dependent case are the same.
     """
     m, r = st.m, st.r
     Gamma = list(Gamma)
@@ -103,10 +117,19 @@ def update_least_squares(st, Gamma, y, eps):
     if not is_dependent(Gamma_r, Gamma, eps_r):
         nrm2 = sum((v * v for v in Gamma_r), z)
         K = [v / nrm2 for v in Gamma_r]
-        st.C.append(list(Gamma))
-        st.Ct = [[st.Ct[k][j] - gamma[k] * K[j] for j in range(m)] for k in range(r)]
-        st.Ct.append(list(K))
-        st.Pinv = [row + [z] for row in st.Pinv] + [[z] * r + [z + 1]]
+        if st.variant == "base":
+            st.C.append(list(Gamma))
+            st.Ct = [[st.Ct[k][j] - gamma[k] * K[j] for j in range(m)] for k in range(r)]
+            st.Ct.append(list(K))
+            st.Pinv = [row + [z] for row in st.Pinv] + [[z] * r + [z + 1]]
+        else:
+            alpha = (z + 1) if st.variant == "orthogonal" else (z + 1) / math.sqrt(nrm2)
+            zeta = [sum((st.Pinv[i][k] * gamma[k] for k in range(r)), z) for i in range(r)]
+            gz = sum((gamma[k] * zeta[k] for k in range(r)), z)
+            st.C.append([alpha * v for v in Gamma_r])
+            st.Ct.append([v / (alpha * nrm2) for v in Gamma_r])
+            st.Pinv = ([st.Pinv[i] + [-alpha * zeta[i]] for i in range(r)]
+                       + [[-alpha * zeta[k] for k in range(r)] + [alpha * alpha * ((z + 1) + gz)]])
         indep = True
     else:
         zeta = [sum((st.Pinv[i][k] * gamma[k] for k in range(r)), z) for i in range(r)]
@@ -119,22 +142,25 @@ def update_least_squares(st, Gamma, y, eps):
     return indep
 
 
-def solve_stream(A, Y, eps=None, exact=False):
+def solve_stream(A, Y, eps=None, exact=False, variant="base"):
     """Push the rows of A (n x m) with targets Y through Algorithm 1.
 
     exact=True runs over Fractions with the exact zero test (eps = 0).
     Otherwise floats; eps=None uses the paper's default threshold with
-    eps_M = 2^-52 evaluated at the current rank.
+    eps_M = 2^-52 evaluated at the current rank.  variant selects the rank
+    factorization: "base" (C = raw rows), "orthogonal" or "orthonormal".
     Returns the final RGState (X, C, Ct, Pinv, decisions).
     """
     n = len(A)
     m = len(A[0]) if n else 0
     if exact:
-        st = RGState(m, Fraction(0))
+        if variant == "orthonormal":
+            raise ValueError("the orthonormal variant takes square roots: not rational")
+        st = RGState(m, Fraction(0), variant)
         for i in range(n):
             update_least_squares(st, [Fraction(v) for v in A[i]], Fraction(Y[i]), 0)
         return st
-    st = RGState(m, 0.0)
+    st = RGState(m, 0.0, variant)
     if eps is None:
         eps = lambda r: default_eps(m, r, 2.0 ** -52)
     for i in range(n):
