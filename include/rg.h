@@ -69,6 +69,13 @@ typedef enum { RG_F32 = 0, RG_F64 = 1 } rg_dtype;
                                        Algorithm 1 (reference path for the blocked variant) */
 #define RG_OPT_DEPENDENT_BLOCKS_ONLY 0x10u  /* blocks take dependent rows only; independent
                                               rows are taken one at a time */
+#define RG_OPT_ORTHOGONAL     0x20u  /* orthogonal rank factorization (Section 2.2, alpha = 1):
+                                       C stores the rejections Gamma_r, whose rows are
+                                       mutually orthogonal; same x and rank as Algorithm 1 */
+#define RG_OPT_ORTHONORMAL    0x40u  /* orthonormal variant (alpha = 1 / ||Gamma_r||): C has
+                                       orthonormal rows and C-tilde = C.  Streams with either
+                                       variant bit run in the global-memory kernel; setting
+                                       both bits is RG_E_INVALID */
 
 typedef struct {
     int32_t dtype;   /* rg_dtype */

@@ -263,6 +263,7 @@ rg_status rg_batch_init(rg_handle *out, int32_t B, const int32_t *m, const int32
     rg_default_options(&o);
     if (opt) o = *opt;
     if (o.dtype != RG_F32 && o.dtype != RG_F64) return RG_E_INVALID;
+    if ((o.flags & RG_OPT_ORTHOGONAL) && (o.flags & RG_OPT_ORTHONORMAL)) return RG_E_INVALID;
     for (int b = 0; b < B; ++b) {
         if (m[b] <= 0) return RG_E_INVALID;
         if (r_max && r_max[b] > m[b]) return RG_E_INVALID;
@@ -285,7 +286,9 @@ rg_status rg_batch_init(rg_handle *out, int32_t B, const int32_t *m, const int32
     // kernel family per stream
     for (int b = 0; b < B; ++b) {
         StreamMeta &M = h->h_meta[b];
-        M.cls = (o.flags & RG_OPT_GENERIC_KERNEL) ? -1 : rg::choose_class(M.m, M.r_max, h->dtype);
+        // the orthogonal factorization variants run in the generic kernel only
+        const bool generic = (o.flags & (RG_OPT_GENERIC_KERNEL | RG_OPT_ORTHOGONAL | RG_OPT_ORTHONORMAL)) != 0;
+        M.cls = generic ? -1 : rg::choose_class(M.m, M.r_max, h->dtype);
         if (M.cls < 0) {
             h->m_max_generic = std::max(h->m_max_generic, M.m);
             h->rmax_max_generic = std::max(h->rmax_max_generic, M.r_max);

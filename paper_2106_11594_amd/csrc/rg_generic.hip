@@ -147,6 +147,44 @@ __device__ void run_stream(const PushArgs<T> &a, int b, double *sG, double *sGr,
                 for (int k = tid; k < r; k += NT) sGam[k] += sGam2[k];
                 __syncthreads();
             }
+            if (a.opts & (OPT_ORTHOGONAL | OPT_ORTHONORMAL)) {
+                // Orthogonal rank factorization (Section 2.2): C gets alpha Gamma_r, Ct gets
+                // Gamma_r / (alpha ||Gamma_r||^2) and keeps its other rows, P^-1 is bordered
+                // with -alpha zeta and alpha^2 (1 + gamma^T zeta), zeta = P^-1 gamma; in
+                // coordinates the new entry of w is alpha (y - gamma^T w).
+                for (int ii = tid; ii < r; ii += NT) {
+                    double acc = 0.0;
+                    for (int k = 0; k < r; ++k) acc += P[(size_t)k * rmax + ii] * sGam[k];
+                    sZ[ii] = acc;
+                }
+                __syncthreads();
+                double gz = 0.0, gw = 0.0;
+                for (int k = tid; k < r; k += NT) {
+                    gz += sGam[k] * sZ[k];
+                    gw += sGam[k] * w[k];
+                }
+                block_sum2(gz, gw, sRed);
+                const bool unit = (a.opts & OPT_ORTHONORMAL) != 0;
+                const double alpha = unit ? 1.0 / sqrt(s) : 1.0;
+                const double inv_as = 1.0 / (alpha * s);
+                for (int j = tid; j < m; j += NT) {
+                    const double cj = alpha * sGr[j];
+                    C[(size_t)r * ldm + j] = (T)cj;
+                    Ct[(size_t)r * ldm + j] = unit ? (T)cj : (T)(sGr[j] * inv_as);
+                }
+                for (int k = tid; k < r; k += NT) {
+                    P[(size_t)r * rmax + k] = -alpha * sZ[k];
+                    P[(size_t)k * rmax + r] = -alpha * sZ[k];
+                }
+                if (tid == 0) {
+                    P[(size_t)r * rmax + r] = alpha * alpha * (1.0 + gz);
+                    w[r] = alpha * (yv - gw);
+                }
+                r += 1;
+                ++applied;
+                __syncthreads();
+                continue;
+            }
             const double inv_s = 1.0 / s;
             for (int j = tid; j < m; j += NT) {
                 const double K = sGr[j] * inv_s;

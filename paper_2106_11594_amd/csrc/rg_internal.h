@@ -26,6 +26,8 @@ constexpr uint32_t FLAG_DENOMINATOR = 0x4u;
 constexpr uint32_t OPT_NO_REPROJECT = 0x1u;
 constexpr uint32_t OPT_ROW_BY_ROW = 0x8u;
 constexpr uint32_t OPT_DEPENDENT_BLOCKS_ONLY = 0x10u;
+constexpr uint32_t OPT_ORTHOGONAL = 0x20u;
+constexpr uint32_t OPT_ORTHONORMAL = 0x40u;
 
 // Arguments of a push launch (by value).
 template <typename T>

@@ -19,6 +19,7 @@ RG_F32, RG_F64 = 0, 1
 FLAG_NONFINITE, FLAG_RANK_CAPACITY, FLAG_DENOMINATOR = 0x1, 0x2, 0x4
 OPT_NO_REPROJECT, OPT_GENERIC_KERNEL, OPT_SERIAL_CLASSES, OPT_ROW_BY_ROW = 0x1, 0x2, 0x4, 0x8
 OPT_DEPENDENT_BLOCKS_ONLY = 0x10
+OPT_ORTHOGONAL, OPT_ORTHONORMAL = 0x20, 0x40
 _STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "HIP runtime error", 4: "unsupported size"}
 
 
