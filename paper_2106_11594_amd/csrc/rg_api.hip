@@ -30,6 +30,7 @@ struct rg_ctx {
     void *d_state = nullptr;
     double *d_p = nullptr;
     double *d_w = nullptr;
+    double *d_big = nullptr;     // scratch of the multi-CU single-stream path (null if unused)
     std::vector<StreamMeta> h_meta;
     std::vector<int64_t> cost;
     // per-family segments of d_order
@@ -80,13 +81,14 @@ Layout plan_layout(int32_t B, const int32_t *m, const int32_t *r_max, size_t esi
     return L;
 }
 
-size_t ws_size(const Layout &L, int B, size_t esize) {
+size_t ws_size(const Layout &L, int B, size_t esize, size_t big_doubles) {
     size_t off = align_up(sizeof(StreamMeta) * (size_t)B, 256);
     off += align_up(sizeof(int32_t) * (size_t)B, 256);
     off += 256;  // counters
     off += align_up(L.state_elems * esize, 256);
     off += align_up(L.p_elems * sizeof(double), 256);
     off += align_up(L.w_elems * sizeof(double), 256);
+    off += align_up(big_doubles * sizeof(double), 256);
     return off;
 }
 
@@ -173,7 +175,10 @@ rg_status push_impl(rg_ctx *h, const void *gamma, const void *y, const int64_t *
     if (!serial)
         for (int f = 1; f < RG_MAX_FAMILIES; ++f)
             if (h->fam_count[f] > 0) HIPCHK(hipStreamWaitEvent(h->stream, h->join[f], 0));
-    if (h->fam_count[0] > 0) {
+    if (h->fam_count[0] > 0 && h->d_big && !row_ptr) {
+        const StreamMeta &M = h->h_meta[0];
+        HIPCHK(rg::launch_push_big<T>(a, h->d_big, M.m, M.r_max, h->num_cus, h->stream));
+    } else if (h->fam_count[0] > 0) {
         a.order = h->d_order + h->fam_begin[0];
         a.n_order = h->fam_count[0];
         a.counter = h->d_counter;
@@ -252,7 +257,9 @@ size_t rg_workspace_bytes(int32_t B, const int32_t *m, const int32_t *r_max, int
         if (m[b] <= 0) return 0;
     const size_t es = dtype == RG_F64 ? 8 : 4;
     Layout L = plan_layout(B, m, r_max, es);
-    return ws_size(L, B, es);
+    const StreamMeta &M0 = L.meta[0];
+    const bool big = B == 1 && M0.m >= rg::BIG_M_MIN && rg::choose_class(M0.m, M0.r_max, dtype) < 0;
+    return ws_size(L, B, es, big ? rg::big_scratch_doubles(M0.m, M0.r_max) : 0);
 }
 
 rg_status rg_batch_init(rg_handle *out, int32_t B, const int32_t *m, const int32_t *r_max, const rg_options *opt) {
@@ -301,7 +308,12 @@ rg_status rg_batch_init(rg_handle *out, int32_t B, const int32_t *m, const int32
         delete h;
         return RG_E_UNSUPPORTED;
     }
-    h->ws_bytes = ws_size(L, B, h->esize);
+    // one large stream that no on-chip class holds runs over the whole GPU
+    const StreamMeta &M0 = h->h_meta[0];
+    const bool big = B == 1 && M0.cls < 0 && M0.m >= rg::BIG_M_MIN &&
+                     !(o.flags & (RG_OPT_GENERIC_KERNEL | RG_OPT_ORTHOGONAL | RG_OPT_ORTHONORMAL));
+    const size_t big_doubles = big ? rg::big_scratch_doubles(M0.m, M0.r_max) : 0;
+    h->ws_bytes = ws_size(L, B, h->esize, big_doubles);
     if (hipMalloc(&h->ws, h->ws_bytes) != hipSuccess) {
         h->ws = nullptr;
         delete h;
@@ -319,6 +331,8 @@ rg_status rg_batch_init(rg_handle *out, int32_t B, const int32_t *m, const int32
     h->d_p = (double *)p;
     p += align_up(L.p_elems * sizeof(double), 256);
     h->d_w = (double *)p;
+    p += align_up(L.w_elems * sizeof(double), 256);
+    if (big) h->d_big = (double *)p;
     rg_status st = RG_OK;
     if (hipMemsetAsync(h->ws, 0, h->ws_bytes, h->stream) != hipSuccess ||
         hipMemcpyAsync(h->d_meta, h->h_meta.data(), sizeof(StreamMeta) * B, hipMemcpyHostToDevice, h->stream) !=

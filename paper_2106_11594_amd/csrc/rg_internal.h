@@ -53,6 +53,12 @@ template <typename T>
 hipError_t launch_push_generic(const PushArgs<T> &a, int grid, int m_max, int r_max_max, hipStream_t s);
 hipError_t launch_reset_counter(uint32_t *counter, hipStream_t s);
 hipError_t launch_reset_streams(StreamMeta *meta, int B, hipStream_t s);
+// One large stream over the whole GPU (rg_big.hip): streams of single-stream
+// handles with m >= BIG_M_MIN that no on-chip class holds.
+constexpr int BIG_M_MIN = 512;
+size_t big_scratch_doubles(int m, int rmax);
+template <typename T>
+hipError_t launch_push_big(const PushArgs<T> &a, double *scratch, int m, int rmax, int num_cus, hipStream_t s);
 template <typename T>
 hipError_t launch_solution(const StreamMeta *meta, int B, const T *state, const double *wreg, T *x,
                            hipStream_t s);
