@@ -63,3 +63,22 @@ def test_workspace_bytes_layout():
     assert b32 >= state32 and b64 >= 2 * state32
     assert rg.workspace_bytes([64], None) > rg.workspace_bytes([64], [16])
     assert rg.workspace_bytes([0]) == 0
+
+
+def test_option_and_flag_bits_match_the_header():
+    """Every RG_OPT_* / RG_FLAG_* value in include/rg.h equals the binding's."""
+    import os
+    import re
+    hdr = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "rg.h")).read()
+    vals = {n: int(v, 16) for n, v in re.findall(r"#define (RG_(?:OPT|FLAG)_\w+)\s+(0x[0-9a-fA-F]+)u", hdr)}
+    assert len(vals) >= 10
+    for n, v in vals.items():
+        assert getattr(rg, n[3:]) == v, n
+
+
+def test_both_variant_bits_are_rejected_before_the_device(L):
+    o = rg.Options()
+    L.rg_default_options(ctypes.byref(o))
+    o.flags = rg.OPT_ORTHOGONAL | rg.OPT_ORTHONORMAL
+    h = ctypes.c_void_p()
+    assert L.rg_init(ctypes.byref(h), 8, ctypes.byref(o)) == 1
