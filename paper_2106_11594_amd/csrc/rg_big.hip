@@ -7,10 +7,11 @@
 //                                      split over its 4 waves; partial norms;
 //                                      in pass 1 also partial zeta = P^-1 gamma
 //                                      over a slice of the rows of P^-1
-//   dec    rank test of Section 3 on the summed partials (one workgroup);
-//          dependent rows: zeta = P^-1 gamma, d = 1 + gamma^T zeta and the
-//          step (y - gamma^T w) / d (Theorems 5, 6)
-//   proj, rej again for an independent row ("twice is enough")
+//   proj   pass 2: workgroup 0 takes the decision (rank test of Section 3
+//          on the summed partials; for a dependent row zeta = P^-1 gamma,
+//          d = 1 + gamma^T zeta and the step (y - gamma^T w) / d, Theorems 5
+//          and 6); for an independent row every workgroup projects Gamma_r
+//   rej    pass 2 for an independent row ("twice is enough")
 //   apply  dependent: P^-1 -= zeta zeta^T / d, w += zeta (y - gamma^T w) / d;
 //          independent: Ct <- [Ct - gamma K^T; K^T], C <- [C; Gamma],
 //          P^-1 <- diag(P^-1, 1), w <- [w; y] (Theorems 4, 6)
@@ -78,104 +79,34 @@ __global__ void k_big_end(StreamMeta *meta, const int32_t *rs, int parity) {
     }
 }
 
-// dst[k] = sum_j Ct[k][j] v[j] for k < r; v is row i of the input (pass 1)
-// or Gamma_r (pass 2, only for an independent row with r > 0).
+// Whether row i is independent and takes the second projection, from the
+// pass-1 partial sums (every workgroup gets the same answer).
 template <typename T>
-__global__ void __launch_bounds__(BT) k_big_proj(PushArgs<T> a, BigArgs b, int64_t i, int pass) {
-    const BigState<T> s = big_state(a);
-    const int r = b.rs[i & 1];
-    if (a.meta->flags != 0u) return;
-    if (pass == 2 && !(b.sc[0] == MODE_IND && b.sc[6] != 0.0)) return;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const T *g = a.gamma + i * (int64_t)s.m;
-    double *dst = pass == 1 ? b.gam : b.gam2;
-    for (int k = blockIdx.x * (BT / 64) + wid; k < r; k += gridDim.x * (BT / 64)) {
-        const T *row = s.Ct + (size_t)k * s.ldm;
-        double acc = 0.0;
-        if (pass == 1) {
-            for (int j = lane; j < s.m; j += 64) acc += (double)row[j] * (double)g[j];
-        } else {
-            for (int j = lane; j < s.m; j += 64) acc += (double)row[j] * b.gr[j];
-        }
-        acc = sum64(acc);
-        if (lane == 0) dst[k] = acc;
-    }
-}
-
-// Gamma_r[j] = v[j] - sum_{k<r} C[k][j] g[k] for the 64 columns of this
-// workgroup (the k range split over the 4 waves); partial sums of Gamma_r^2
-// (and, in pass 1, of Gamma^2 and of non-finite entries) per workgroup.
-template <typename T>
-__global__ void __launch_bounds__(BT) k_big_rej(PushArgs<T> a, BigArgs b, int64_t i, int pass) {
-    __shared__ double red[BT / 64][64];
-    const BigState<T> s = big_state(a);
-    const int r = b.rs[i & 1];
-    if (a.meta->flags != 0u) return;
-    if (pass == 2 && !(b.sc[0] == MODE_IND && b.sc[6] != 0.0)) return;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int col = blockIdx.x * 64 + lane;
-    const double *g = pass == 1 ? b.gam : b.gam2;
-    double acc = 0.0;
-    if (col < s.m) {
-#pragma unroll 8
-        for (int k = wid; k < r; k += BT / 64) acc += (double)s.C[(size_t)k * s.ldm + col] * g[k];
-    }
-    red[wid][lane] = acc;
-    __syncthreads();
+__device__ inline bool second_pass(const PushArgs<T> &a, const BigArgs &b, int m, int rmax, int r, int64_t i) {
     double sr = 0.0, sg = 0.0, sb = 0.0;
-    if (wid == 0) {
-        if (col < s.m) {
-            double t = 0.0;
-#pragma unroll
-            for (int q = 0; q < BT / 64; ++q) t += red[q][lane];
-            double v;
-            if (pass == 1) {
-                v = (double)a.gamma[i * (int64_t)s.m + col];
-                sg = v * v;
-                sb = isfinite(v) ? 0.0 : 1.0;
-            } else {
-                v = b.gr[col];
-            }
-            const double rv = v - t;
-            b.gr[col] = rv;
-            sr = rv * rv;
-        }
-        sr = sum64(sr);
-        sg = sum64(sg);
-        sb = sum64(sb);
-        if (lane == 0) {
-            double *pp = b.part + (size_t)(pass == 1 ? 0 : b.np) * 4 + (size_t)blockIdx.x * 4;
-            pp[0] = sr;
-            pp[1] = sg;
-            pp[2] = sb;
-        }
+    for (int q = 0; q < b.np; ++q) {  // fixed order
+        sr += b.part[4 * q];
+        sg += b.part[4 * q + 1];
+        sb += b.part[4 * q + 2];
     }
-    if (pass == 1) {
-        // partial zeta[ii] = sum over this workgroup's rows k of P^-1[k][ii] gamma_k
-        // (P^-1 is symmetric; row reads coalesce); used if the row is dependent
-        const int per = (r + b.np - 1) / b.np, k0 = blockIdx.x * per, k1 = min(r, k0 + per);
-        for (int ii = threadIdx.x; ii < r; ii += BT) {
-            double z = 0.0;
-            for (int k = k0; k < k1; ++k) z += s.P[(size_t)k * s.rmax + ii] * b.gam[k];
-            b.zpart[(size_t)blockIdx.x * s.rmax + ii] = z;
-        }
-    }
+    const double yv = (double)a.y[i];
+    if (sb != 0.0 || !isfinite(sg) || !isfinite(yv)) return false;
+    const double eps = a.eps >= 0.0 ? a.eps : ((double)m * m * r + (double)m * r + (double)m) * 0x1p-52;
+    const double nr = sqrt(sr), ng = sqrt(sg);
+    const bool dependent = (sr == 0.0) || (nr < eps) || (nr < eps * ng);
+    return !dependent && r < rmax && r > 0 && !(a.opts & OPT_NO_REPROJECT);
 }
 
-// Rank test and the dependent-row scalars (one workgroup).
+// Rank test and the dependent-row scalars (one workgroup: workgroup 0 of the
+// second-pass projection launch).  Writes the decision read by apply.
 template <typename T>
-__global__ void __launch_bounds__(BT) k_big_dec(PushArgs<T> a, BigArgs b, int64_t i) {
-    __shared__ double sred[2 * (BT / 64)];
+__device__ void big_decide(const PushArgs<T> &a, const BigArgs &b, int64_t i, double *sred) {
     const BigState<T> s = big_state(a);
     StreamMeta *M = a.meta;
     const int r = b.rs[i & 1];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    if (M->flags != 0u) {
-        if (tid == 0) b.sc[0] = MODE_NONE;
-        return;
-    }
     double sr = 0.0, sg = 0.0, sb = 0.0;
-    for (int q = 0; q < b.np; ++q) {  // fixed order
+    for (int q = 0; q < b.np; ++q) {  // fixed order (the same sums as second_pass)
         sr += b.part[4 * q];
         sg += b.part[4 * q + 1];
         sb += b.part[4 * q + 2];
@@ -239,6 +170,100 @@ __global__ void __launch_bounds__(BT) k_big_dec(PushArgs<T> a, BigArgs b, int64_
         b.sc[6] = (mode == MODE_IND && r > 0 && !(a.opts & OPT_NO_REPROJECT)) ? 1.0 : 0.0;
         if (flag) M->flags = flag;
         else b.rs[2] += 1;  // the row is applied (a dependent row at rank 0 is a no-op)
+    }
+}
+
+// dst[k] = sum_j Ct[k][j] v[j] for k < r; v is row i of the input (pass 1)
+// or Gamma_r (pass 2, only for an independent row with r > 0).  In pass 2
+// workgroup 0 first takes the decision of the row.
+template <typename T>
+__global__ void __launch_bounds__(BT) k_big_proj(PushArgs<T> a, BigArgs b, int64_t i, int pass) {
+    __shared__ double sred[2 * (BT / 64)];
+    const BigState<T> s = big_state(a);
+    const int r = b.rs[i & 1];
+    if (a.meta->flags != 0u) {
+        if (pass == 2 && blockIdx.x == 0 && threadIdx.x == 0) b.sc[0] = MODE_NONE;
+        return;
+    }
+    if (pass == 2) {
+        // the flags are re-read after this point by no workgroup of this launch
+        const bool two = second_pass(a, b, s.m, s.rmax, r, i);
+        if (blockIdx.x == 0) big_decide(a, b, i, sred);
+        if (!two) return;
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const T *g = a.gamma + i * (int64_t)s.m;
+    double *dst = pass == 1 ? b.gam : b.gam2;
+    for (int k = blockIdx.x * (BT / 64) + wid; k < r; k += gridDim.x * (BT / 64)) {
+        const T *row = s.Ct + (size_t)k * s.ldm;
+        double acc = 0.0;
+        if (pass == 1) {
+            for (int j = lane; j < s.m; j += 64) acc += (double)row[j] * (double)g[j];
+        } else {
+            for (int j = lane; j < s.m; j += 64) acc += (double)row[j] * b.gr[j];
+        }
+        acc = sum64(acc);
+        if (lane == 0) dst[k] = acc;
+    }
+}
+
+// Gamma_r[j] = v[j] - sum_{k<r} C[k][j] g[k] for the 64 columns of this
+// workgroup (the k range split over the 4 waves); partial sums of Gamma_r^2
+// (and, in pass 1, of Gamma^2 and of non-finite entries) per workgroup.
+template <typename T>
+__global__ void __launch_bounds__(BT) k_big_rej(PushArgs<T> a, BigArgs b, int64_t i, int pass) {
+    __shared__ double red[BT / 64][64];
+    const BigState<T> s = big_state(a);
+    const int r = b.rs[i & 1];
+    if (a.meta->flags != 0u) return;
+    if (pass == 2 && !second_pass(a, b, s.m, s.rmax, r, i)) return;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int col = blockIdx.x * 64 + lane;
+    const double *g = pass == 1 ? b.gam : b.gam2;
+    double acc = 0.0;
+    if (col < s.m) {
+#pragma unroll 8
+        for (int k = wid; k < r; k += BT / 64) acc += (double)s.C[(size_t)k * s.ldm + col] * g[k];
+    }
+    red[wid][lane] = acc;
+    __syncthreads();
+    double sr = 0.0, sg = 0.0, sb = 0.0;
+    if (wid == 0) {
+        if (col < s.m) {
+            double t = 0.0;
+#pragma unroll
+            for (int q = 0; q < BT / 64; ++q) t += red[q][lane];
+            double v;
+            if (pass == 1) {
+                v = (double)a.gamma[i * (int64_t)s.m + col];
+                sg = v * v;
+                sb = isfinite(v) ? 0.0 : 1.0;
+            } else {
+                v = b.gr[col];
+            }
+            const double rv = v - t;
+            b.gr[col] = rv;
+            sr = rv * rv;
+        }
+        sr = sum64(sr);
+        sg = sum64(sg);
+        sb = sum64(sb);
+        if (lane == 0) {
+            double *pp = b.part + (size_t)(pass == 1 ? 0 : b.np) * 4 + (size_t)blockIdx.x * 4;
+            pp[0] = sr;
+            pp[1] = sg;
+            pp[2] = sb;
+        }
+    }
+    if (pass == 1) {
+        // partial zeta[ii] = sum over this workgroup's rows k of P^-1[k][ii] gamma_k
+        // (P^-1 is symmetric; row reads coalesce); used if the row is dependent
+        const int per = (r + b.np - 1) / b.np, k0 = blockIdx.x * per, k1 = min(r, k0 + per);
+        for (int ii = threadIdx.x; ii < r; ii += BT) {
+            double z = 0.0;
+            for (int k = k0; k < k1; ++k) z += s.P[(size_t)k * s.rmax + ii] * b.gam[k];
+            b.zpart[(size_t)blockIdx.x * s.rmax + ii] = z;
+        }
     }
 }
 
@@ -321,7 +346,6 @@ hipError_t launch_push_big(const PushArgs<T> &a, double *scratch, int m, int rma
     for (int64_t i = 0; i < a.k_single; ++i) {
         hipLaunchKernelGGL(k_big_proj<T>, dim3(gproj), dim3(BT), 0, st, a, b, i, 1);
         hipLaunchKernelGGL(k_big_rej<T>, dim3(b.np), dim3(BT), 0, st, a, b, i, 1);
-        hipLaunchKernelGGL(k_big_dec<T>, dim3(1), dim3(BT), 0, st, a, b, i);
         hipLaunchKernelGGL(k_big_proj<T>, dim3(gproj), dim3(BT), 0, st, a, b, i, 2);
         hipLaunchKernelGGL(k_big_rej<T>, dim3(b.np), dim3(BT), 0, st, a, b, i, 2);
         hipLaunchKernelGGL(k_big_apply<T>, dim3(gapply), dim3(BT), 0, st, a, b, i);
