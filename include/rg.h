@@ -173,6 +173,15 @@ rg_status rg_batch_get_state(rg_handle h, int32_t b, void *C, void *Ct, void *Pi
 rg_status rg_batch_adjoint(rg_handle h, const void *A, const void *Y, const int64_t *row_ptr,
                            const int64_t *a_off, const void *g, void *dA, void *dY);
 
+/* Pseudoinverse of every stream from its maintained factorisation (Theorem 1:
+ * A^+ = Ct^T P^-1 B^T with B = A Ct^T): given the rows A that were pushed since
+ * the last reset (device, laid out as in rg_batch_push), write A^+ of stream b
+ * (device, m_b x n_b row-major, at element offset a_off[b], i.e. the same
+ * number of elements and offset as the stream's rows; n_b = row_ptr[b+1] -
+ * row_ptr[b]).  FP64 sums, stored in the handle dtype.  O(n m r) per stream;
+ * stream-ordered. */
+rg_status rg_batch_pinv(rg_handle h, const void *A, const int64_t *row_ptr, const int64_t *a_off, void *Ap);
+
 /* ---- kernel size classes (tuning) -------------------------------------- */
 
 /* FP32 streams run in one of rg_class_count() on-chip kernel classes, or in

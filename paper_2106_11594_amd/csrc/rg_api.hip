@@ -481,6 +481,17 @@ rg_status rg_batch_adjoint(rg_handle h, const void *A, const void *Y, const int6
     return e == hipSuccess ? RG_OK : RG_E_DEVICE;
 }
 
+rg_status rg_batch_pinv(rg_handle h, const void *A, const int64_t *row_ptr, const int64_t *a_off, void *Ap) {
+    if (!valid_handle(h) || !A || !row_ptr || !a_off || !Ap) return RG_E_INVALID;
+    hipError_t e =
+        h->dtype == RG_F64
+            ? rg::launch_pinv<double>(h->d_meta, h->B, (const double *)h->d_state, h->d_p, (const double *)A, row_ptr,
+                                      a_off, (double *)Ap, h->m_max_all, h->rmax_max_all, h->stream)
+            : rg::launch_pinv<float>(h->d_meta, h->B, (const float *)h->d_state, h->d_p, (const float *)A, row_ptr,
+                                     a_off, (float *)Ap, h->m_max_all, h->rmax_max_all, h->stream);
+    return e == hipSuccess ? RG_OK : RG_E_DEVICE;
+}
+
 rg_status rg_destroy(rg_handle h) {
     if (!h) return RG_E_INVALID;
     rg_status st = RG_OK;

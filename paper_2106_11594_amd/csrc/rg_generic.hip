@@ -391,7 +391,59 @@ __global__ void __launch_bounds__(NT) k_adjoint(const StreamMeta *meta, const T 
     }
 }
 
+// Pseudoinverse of stream b from its factorisation (Theorem 1:
+// A^+ = Ct^T P^-1 B^T with B = A Ct^T), one row of A at a time: column i of
+// A^+ is Ct^T P^-1 (Ct A_i^T).  FP64 sums; A^+ is m x n row-major.
+template <typename T>
+__global__ void __launch_bounds__(NT) k_pinv(const StreamMeta *meta, const T *state, const double *preg, const T *A,
+                                             const int64_t *row_ptr, const int64_t *a_off, T *Ap, int m_max,
+                                             int r_max_max) {
+    extern __shared__ double smem[];
+    const int b = blockIdx.x;
+    const StreamMeta M = meta[b];
+    const int m = M.m, r = M.r, ldm = M.ldm, rmax = M.r_max;
+    const T *Ct = state + M.state_off + (size_t)rmax * ldm;
+    const double *P = preg + M.p_off;
+    double *sa = smem, *sb = sa + m_max, *sq = sb + r_max_max;
+    const int64_t i0 = row_ptr[b], i1 = row_ptr[b + 1], n = i1 - i0;
+    const T *Ab = A + a_off[b];
+    T *Apb = Ap + a_off[b];
+    const int tid = threadIdx.x;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int j = tid; j < m; j += NT) sa[j] = (double)Ab[i * m + j];
+        __syncthreads();
+        project<T, double>(Ct, ldm, sa, sb, r, m);  // b = Ct A_i^T
+        __syncthreads();
+        for (int a2 = tid; a2 < r; a2 += NT) {       // q = P^-1 b (symmetric: column reads coalesce)
+            double acc = 0.0;
+            for (int k = 0; k < r; ++k) acc += P[(size_t)k * rmax + a2] * sb[k];
+            sq[a2] = acc;
+        }
+        __syncthreads();
+        for (int j = tid; j < m; j += NT) {
+            double acc = 0.0;
+            for (int k = 0; k < r; ++k) acc += (double)Ct[(size_t)k * ldm + j] * sq[k];
+            Apb[(int64_t)j * n + i] = (T)acc;
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace
+
+template <typename T>
+hipError_t launch_pinv(const StreamMeta *meta, int B, const T *state, const double *preg, const T *A,
+                       const int64_t *row_ptr, const int64_t *a_off, T *Ap, int m_max, int r_max_max, hipStream_t s) {
+    const size_t lds = sizeof(double) * ((size_t)m_max + 2 * (size_t)r_max_max);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_pinv<T>, dim3(B), dim3(NT), lds, s, meta, state, preg, A, row_ptr, a_off, Ap, m_max,
+                       r_max_max);
+    return hipGetLastError();
+}
+template hipError_t launch_pinv<float>(const StreamMeta *, int, const float *, const double *, const float *,
+                                       const int64_t *, const int64_t *, float *, int, int, hipStream_t);
+template hipError_t launch_pinv<double>(const StreamMeta *, int, const double *, const double *, const double *,
+                                        const int64_t *, const int64_t *, double *, int, int, hipStream_t);
 
 template <typename T>
 hipError_t launch_push_generic(const PushArgs<T> &a, int grid, int m_max, int r_max_max, hipStream_t s) {

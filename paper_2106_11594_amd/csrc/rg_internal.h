@@ -60,6 +60,9 @@ size_t big_scratch_doubles(int m, int rmax);
 template <typename T>
 hipError_t launch_push_big(const PushArgs<T> &a, double *scratch, int m, int rmax, int num_cus, hipStream_t s);
 template <typename T>
+hipError_t launch_pinv(const StreamMeta *meta, int B, const T *state, const double *preg, const T *A,
+                       const int64_t *row_ptr, const int64_t *a_off, T *Ap, int m_max, int r_max_max, hipStream_t s);
+template <typename T>
 hipError_t launch_solution(const StreamMeta *meta, int B, const T *state, const double *wreg, T *x,
                            hipStream_t s);
 template <typename T>

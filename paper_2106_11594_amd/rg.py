@@ -56,6 +56,7 @@ _SIGS = {
     "rg_batch_flags": (ctypes.c_int, [_p, _p]),
     "rg_batch_get_state": (ctypes.c_int, [_p, _i32, _p, _p, _p, _p]),
     "rg_batch_adjoint": (ctypes.c_int, [_p, _p, _p, _p, _p, _p, _p, _p]),
+    "rg_batch_pinv": (ctypes.c_int, [_p, _p, _p, _p, _p]),
     "rg_workspace_bytes": (ctypes.c_size_t, [_i32, _p, _p, _i32]),
     "rg_class_count": (_i32, []),
     "rg_class_info": (ctypes.c_int, [_i32, _p, _p, _p]),
@@ -212,6 +213,18 @@ class Batch:
                                       _dev(dA, self.tdtype, "dA", A.numel()),
                                       _dev(dY, self.tdtype, "dY", Y.numel())), "rg_batch_adjoint")
         return dA, dY
+
+    def pinv(self, A, row_ptr, a_off, out=None):
+        """A^+ of every stream (Theorem 1), packed like A: stream b's m x n_b
+        pseudoinverse, row-major, at a_off[b]."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty_like(A)
+        _check(lib().rg_batch_pinv(self._h, _dev(A, self.tdtype, "A"),
+                                   _dev(row_ptr, torch.int64, "row_ptr", self.B + 1),
+                                   _dev(a_off, torch.int64, "a_off", self.B),
+                                   _dev(out, self.tdtype, "Ap", A.numel())), "rg_batch_pinv")
+        return out
 
     def close(self):
         if getattr(self, "_h", None):
