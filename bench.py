@@ -158,8 +158,8 @@ def main():
                          "reference point for HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on exactly one GPU: the batched streams are independent and this build "
-              "has no multi-GPU path; streams would be partitioned across GPUs by cost with no exchange.", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the batched streams are independent and there is "
+              "no multi-GPU path; streams would be partitioned across GPUs by cost with no exchange.", file=sys.stderr)
         sys.exit(2)
 
     import torch

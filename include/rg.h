@@ -50,7 +50,7 @@ typedef enum {
     RG_E_INVALID = 1,       /* bad argument; nothing was done */
     RG_E_NOMEM = 2,         /* device or host allocation failed (init only) */
     RG_E_DEVICE = 3,        /* a HIP runtime call failed */
-    RG_E_UNSUPPORTED = 4    /* valid request outside this build's limits */
+    RG_E_UNSUPPORTED = 4    /* valid request outside the library's limits */
 } rg_status;
 
 typedef enum { RG_F32 = 0, RG_F64 = 1 } rg_dtype;
