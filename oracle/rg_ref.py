@@ -18,6 +18,9 @@ Pins (all in tests/test_oracle_*.py): the Fraction run equals the independent
 exact solver ``lstsq_exact`` bit for bit; hand-derived worked examples; the
 Penrose equations on the pseudoinverse rebuilt by Theorem 1; truncated-SVD
 solutions; closed forms for a single row, A = I and full column rank.  The
+maintained pseudoinverse of Theorems 2 and 3 (``track_pinv``) is pinned in
+tests/test_oracle_pinv_update.py: exact Penrose equations and B C = A on
+Fraction runs, the closed form of [I_n; 1^T], the SVD pseudoinverse in FP64.  The
 orthogonal rank factorization variants of Section 2.2 (``variant=``) are
 pinned in tests/test_oracle_variants.py: exactly against the same solver and
 factor invariants for alpha = 1, in FP64 for the orthonormal one.
@@ -41,12 +44,18 @@ class RGState:
     Gamma_r = Gamma).
     """
 
-    def __init__(self, m, zero, variant="base"):
+    def __init__(self, m, zero, variant="base", track_pinv=False):
         if variant not in ("base", "orthogonal", "orthonormal"):
             raise ValueError(variant)
         self.m = m
         self.zero = zero
         self.variant = variant
+        # Theorems 2 and 3 (optional): the pseudoinverse A_n^+ (m x n, list of m
+        # rows) and the coordinate factor B_n (n x r, list of n rows) with
+        # A_n = B_n C_n, both maintained row by row.
+        self.track_pinv = track_pinv
+        self.Ap = [[] for _ in range(m)] if track_pinv else None
+        self.B = [] if track_pinv else None
         self.X = [zero] * m
         self.C = []      # list of rows (length m)
         self.Ct = []     # list of rows (length m)
@@ -96,6 +105,14 @@ def update_least_squares(st, Gamma, y, eps):
     Both: X <- X + K (y - Gamma^T X), with the X from before this row.
     Returns True when the row was independent.
 
+    With ``st.track_pinv`` the same K also updates the pseudoinverse
+    (Theorem 2, independent; Theorem 3, dependent):
+    A^+ <- [A^+ 0] + K (-beta^T, 1), beta = B zeta, zeta = Pinv gamma, with B
+    and Pinv from before this row.  The new row of B holds the coordinates of
+    Gamma in the new basis: gamma (dependent), e_{r+1} (base factorization,
+    where Gamma itself joins C; old rows gain a zero), or (gamma, 1/alpha)
+    (Section 2.2, where alpha Gamma_r joins C).
+
     Orthogonal rank factorization (Section 2.2): the
     independent case stores a rescaled rejection alpha Gamma_r in C instead of
     Gamma, appends Gamma_r / (alpha ||Gamma_r||^2) to Ct without touching its
@@ -114,6 +131,9 @@ def update_least_squares(st, Gamma, y, eps):
     eps_r = eps(r) if callable(eps) else eps
     # a priori residual, taken before X changes
     dy = y - sum((Gamma[j] * st.X[j] for j in range(m)), z)
+    if st.track_pinv:
+        zeta_old = [sum((st.Pinv[i][k] * gamma[k] for k in range(r)), z) for i in range(r)]
+        beta = [sum((st.B[i][k] * zeta_old[k] for k in range(r)), z) for i in range(len(st.B))]
     if not is_dependent(Gamma_r, Gamma, eps_r):
         nrm2 = sum((v * v for v in Gamma_r), z)
         K = [v / nrm2 for v in Gamma_r]
@@ -137,30 +157,39 @@ def update_least_squares(st, Gamma, y, eps):
         K = [sum((st.Ct[k][j] * zeta[k] for k in range(r)), z) / den for j in range(m)]
         st.Pinv = [[st.Pinv[i][k] - zeta[i] * zeta[k] / den for k in range(r)] for i in range(r)]
         indep = False
+    if st.track_pinv:
+        st.Ap = [[st.Ap[j][i] - K[j] * beta[i] for i in range(len(beta))] + [K[j]] for j in range(m)]
+        if not indep:
+            st.B.append(list(gamma))
+        else:
+            st.B = [row + [z] for row in st.B]
+            last = (z + 1) if st.variant == "base" else (z + 1) / alpha
+            st.B.append(([z] * r if st.variant == "base" else list(gamma)) + [last])
     st.X = [st.X[j] + K[j] * dy for j in range(m)]
     st.decisions.append(indep)
     return indep
 
 
-def solve_stream(A, Y, eps=None, exact=False, variant="base"):
+def solve_stream(A, Y, eps=None, exact=False, variant="base", track_pinv=False):
     """Push the rows of A (n x m) with targets Y through Algorithm 1.
 
     exact=True runs over Fractions with the exact zero test (eps = 0).
     Otherwise floats; eps=None uses the paper's default threshold with
     eps_M = 2^-52 evaluated at the current rank.  variant selects the rank
     factorization: "base" (C = raw rows), "orthogonal" or "orthonormal".
-    Returns the final RGState (X, C, Ct, Pinv, decisions).
+    track_pinv also maintains A^+ and B (Theorems 2 and 3).
+    Returns the final RGState (X, C, Ct, Pinv, decisions[, Ap, B]).
     """
     n = len(A)
     m = len(A[0]) if n else 0
     if exact:
         if variant == "orthonormal":
             raise ValueError("the orthonormal variant takes square roots: not rational")
-        st = RGState(m, Fraction(0), variant)
+        st = RGState(m, Fraction(0), variant, track_pinv)
         for i in range(n):
             update_least_squares(st, [Fraction(v) for v in A[i]], Fraction(Y[i]), 0)
         return st
-    st = RGState(m, 0.0, variant)
+    st = RGState(m, 0.0, variant, track_pinv)
     if eps is None:
         eps = lambda r: default_eps(m, r, 2.0 ** -52)
     for i in range(n):
