@@ -142,6 +142,42 @@ def adjoint_leg(torch, rg, W, steps, warmup):
                                   "algorithmic_bytes": bytes_bw}}
 
 
+def pinv_track_leg(torch, rg, W, steps, warmup, B=256, n=256, m=64, r=16):
+    """Theorems 2 and 3 (A^+ maintained row by row), FP64: B problems of n rows
+    of m regressors at planted rank r, one workgroup each, timed with HIP
+    events on the current stream.  Algorithmic bytes per row i: the A^+ update
+    reads and writes m (i+1) values, beta reads i r_i values of B, the two
+    projections read r_i m values of C and of Ct, plus the row itself."""
+    rng = np.random.default_rng(5)
+    A = np.stack([W.lowrank_rows(rng, m, r, n) for _ in range(B)]).astype(np.float64)
+    Y = np.stack([W.targets(rng, A[b])[0] for b in range(B)]).astype(np.float64)
+    dev = torch.device("cuda:0")
+    Ad = torch.from_numpy(A).to(dev)
+    Yd = torch.from_numpy(Y).to(dev)
+    stream = torch.cuda.current_stream()
+    ts = []
+    for k in range(warmup + steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        Ap, X, rank, flags = rg.pinv_track(Ad, Yd, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if k >= warmup:
+            ts.append(e0.elapsed_time(e1))
+    ri = np.minimum(np.arange(n), r).astype(np.float64)
+    i = np.arange(n, dtype=np.float64)
+    per = float((16.0 * m * (i + 1) + 8.0 * i * ri + 16.0 * m * ri + 8.0 * (m + 1)).sum())
+    ms = float(np.mean(ts))
+    gbs = B * per / (ms * 1e-3) / 1e9
+    return {"workload": "pseudoinverse maintained row by row: B=%d problems, n=%d, m=%d, planted rank %d, FP64"
+                        % (B, n, m, r),
+            "ms": ms, "row_updates_per_s": B * n / (ms * 1e-3),
+            "rank_equal_planted": int((rank.cpu().numpy() == r).sum()), "flags_nonzero":
+                int((flags.cpu().numpy() != 0).sum()), "problems": B,
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": gbs / PEAK_HBM_GBS, "algorithmic_bytes": B * per}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +189,7 @@ def main():
     ap.add_argument("--default-classes", action="store_true",
                     help="ignore the autotuned class rules (paper_2106_11594_amd/class_rules.json)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiable-solve (backward) leg")
+    ap.add_argument("--no-pinv-track", action="store_true", help="skip the recursive pseudoinverse leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the timed steps, run a plain copy kernel (out = -in) over MIB MiB twice, as the "
                          "reference point for HBM byte counters")
@@ -250,6 +287,10 @@ def main():
         print("adjoint leg: forward %.3f ms, backward %.3f ms" % (out["adjoint"]["forward_ms"],
                                                                   out["adjoint"]["backward_ms"]),
               file=sys.stderr, flush=True)
+
+    if not args.no_pinv_track:
+        out["pinv_track"] = pinv_track_leg(torch, rg, W, steps=2, warmup=1)
+        print("pinv_track leg: %.3f ms" % out["pinv_track"]["ms"], file=sys.stderr, flush=True)
 
     if not args.no_cpu:
         from oracle import ref_c

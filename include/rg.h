@@ -182,6 +182,40 @@ rg_status rg_batch_adjoint(rg_handle h, const void *A, const void *Y, const int6
  * stream-ordered. */
 rg_status rg_batch_pinv(rg_handle h, const void *A, const int64_t *row_ptr, const int64_t *a_off, void *Ap);
 
+/* ---- pseudoinverse maintained row by row (Theorems 2 and 3) ----------- */
+
+/* Device bytes of the workspace rg_pinv_track needs (0 for invalid sizes):
+ * per problem C and Ct (r_max x m), P^-1 (r_max x r_max), the coordinate
+ * factor B (n x r_max) of A = B C, and beta (n), all FP64. */
+size_t rg_pinv_track_workspace_bytes(int32_t B, int32_t n, int32_t m, int32_t r_max);
+
+/* Push the n rows of each of B problems (all with n rows of m regressors)
+ * through Algorithm 1 and maintain the pseudoinverse recursively
+ * (Theorem 2, independent row: A^+ <- [A^+ - K beta^T, K] with
+ * K = Gamma_r / ||Gamma_r||^2; Theorem 3, dependent row: the same with
+ * K = Ct^T zeta / (1 + gamma^T zeta); beta = B zeta, zeta = P^-1 gamma).
+ * O(m n) per row, FP64, base rank factorization, one workgroup per problem.
+ *   A     device, B x n x m row-major (row i of problem b at (b n + i) m)
+ *   Y     device, B x n targets
+ *   eps   rank threshold of Section 3; < 0 takes the default
+ *         (m^2 r + m r + m) eps_M at the rank before each row; NaN is invalid
+ *   Ap    device output, B x m x n: A_n^+ of each problem, row-major
+ *   X     device output, B x m: the minimum-norm least-squares solution
+ *   rank  device output, B int32; flags device output, B uint32 (RG_FLAG_*)
+ *   work  device workspace of at least rg_pinv_track_workspace_bytes bytes,
+ *         owned by the caller; its contents on entry do not matter
+ *   stream  hipStream_t to enqueue on (NULL = default stream)
+ * A row that is not finite, an independent row at r == r_max or a
+ * non-positive 1 + gamma^T zeta sets the flag and ends that problem: its later
+ * columns of Ap and its X are then undefined.  r_max <= m; r_max >= min(n, m)
+ * never runs out of capacity in exact arithmetic.  A, Y and Ap may be NULL
+ * when n == 0.  Invalid arguments return RG_E_INVALID before any device work;
+ * LDS needs over 160 KiB (3 m + 2 r_max doubles) return RG_E_UNSUPPORTED.
+ * Stream-ordered; the caller synchronises before reading the outputs. */
+rg_status rg_pinv_track(const double *A, const double *Y, int32_t B, int32_t n, int32_t m, int32_t r_max,
+                        double eps, double *Ap, double *X, int32_t *rank, uint32_t *flags, void *work,
+                        size_t work_bytes, void *stream);
+
 /* ---- kernel size classes (tuning) -------------------------------------- */
 
 /* FP32 streams run in one of rg_class_count() on-chip kernel classes, or in

@@ -1,0 +1,218 @@
+// Pseudoinverse maintained row by row (Theorems 2 and 3), FP64, gfx950.
+//
+// One workgroup (4 wave64) owns one problem of a batch and walks its rows in
+// order.  Per row Gamma (with target y), the update of Algorithm 1 plus the
+// O(m n) pseudoinverse update:
+//   gamma   = Ct Gamma, Gamma_r = Gamma - C^T gamma, rank test of Section 3
+//   zeta    = P^-1 gamma and beta = B zeta, both with the state before the row
+//   gain K  = Gamma_r / ||Gamma_r||^2            (independent, Theorem 2/4)
+//           = Ct^T zeta / (1 + gamma^T zeta)     (dependent, Theorem 3/5)
+//   A^+    <- [A^+ - K beta^T, K]                 (a new column per row)
+//   x      <- x + K (y - Gamma^T x)
+//   factors (Theorem 6): independent appends Gamma to C, K to Ct (after
+//   Ct -= gamma K^T), borders P^-1 with 1 and B with the unit coordinate
+//   e_{r+1}; dependent downdates P^-1 by zeta zeta^T / (1 + gamma^T zeta) and
+//   appends gamma to B.
+// B (n x r_max) is the coordinate factor of A = B C; it is needed only for
+// beta, which is what makes the pseudoinverse update O(m n) per row.
+//
+// The A^+ update reads and writes m x (i+1) values per row i, so the kernel is
+// bound by memory traffic to the L2 / HBM, not by arithmetic: per row it moves
+// about 16 m (i+1) bytes of A^+ plus 8 (i + 3 m r) bytes of B, C and Ct.
+#include "../../include/rg.h"
+#include <hip/hip_runtime.h>
+#include <cfloat>
+#include <cmath>
+
+namespace {
+
+constexpr int NT = 256;
+constexpr int NW = NT / 64;
+
+__device__ inline double wsum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum a, b and c over the workgroup in a fixed order; every thread gets the
+// same totals, so decisions taken on them are uniform.
+__device__ inline void block_sum3(double &a, double &b, double &c, double *red) {
+    a = wsum(a);
+    b = wsum(b);
+    c = wsum(c);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) {
+        red[3 * w] = a;
+        red[3 * w + 1] = b;
+        red[3 * w + 2] = c;
+    }
+    __syncthreads();
+    a = b = c = 0.0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        a += red[3 * i];
+        b += red[3 * i + 1];
+        c += red[3 * i + 2];
+    }
+}
+
+inline size_t per_problem(int n, int m, int rmax) {
+    return 2 * (size_t)rmax * m + (size_t)rmax * rmax + (size_t)n * rmax + (size_t)n;
+}
+
+__global__ void __launch_bounds__(NT) k_pinv_track(const double *A, const double *Y, int n, int m, int rmax,
+                                                   double eps_in, double *Ap, double *X, int32_t *rank,
+                                                   uint32_t *flags, double *work, size_t per) {
+    extern __shared__ double sm[];
+    double *sG = sm, *sR = sG + m, *sK = sR + m, *sg = sK + m, *sz = sg + rmax, *red = sz + rmax;
+    const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    double *C = work + (size_t)b * per;
+    double *Ct = C + (size_t)rmax * m;
+    double *P = Ct + (size_t)rmax * m;
+    double *Bf = P + (size_t)rmax * rmax;
+    double *beta = Bf + (size_t)n * rmax;
+    const double *Ab = A + (size_t)b * n * m;
+    const double *Yb = Y + (size_t)b * n;
+    double *Apb = Ap + (size_t)b * m * n;
+    double *Xb = X + (size_t)b * m;
+
+    // Zero P^-1 and B: bordering then only writes the new diagonal / unit entry.
+    for (size_t t = tid; t < (size_t)rmax * rmax; t += NT) P[t] = 0.0;
+    for (size_t t = tid; t < (size_t)n * rmax; t += NT) Bf[t] = 0.0;
+    for (int j = tid; j < m; j += NT) Xb[j] = 0.0;
+    __syncthreads();
+
+    int r = 0;
+    uint32_t fl = 0;
+    for (int i = 0; i < n; ++i) {
+        const double *G = Ab + (size_t)i * m;
+        const double y = Yb[i];
+        for (int j = tid; j < m; j += NT) sG[j] = G[j];
+        __syncthreads();
+        // gamma = Ct Gamma: one wave per row k of Ct, lanes over j.
+        for (int k = wid; k < r; k += NW) {
+            double acc = 0.0;
+            for (int j = lane; j < m; j += 64) acc += Ct[(size_t)k * m + j] * sG[j];
+            acc = wsum(acc);
+            if (lane == 0) sg[k] = acc;
+        }
+        __syncthreads();
+        // Gamma_r = Gamma - C^T gamma, with ||Gamma_r||^2, ||Gamma||^2 and Gamma^T x.
+        double s = 0.0, g2 = 0.0, gx = 0.0;
+        for (int j = tid; j < m; j += NT) {
+            const double gj = sG[j];
+            double acc = gj;
+            for (int k = 0; k < r; ++k) acc -= C[(size_t)k * m + j] * sg[k];
+            sR[j] = acc;
+            s += acc * acc;
+            g2 += gj * gj;
+            gx += gj * Xb[j];
+        }
+        block_sum3(s, g2, gx, red);
+        if (!isfinite(g2) || !isfinite(y)) {
+            fl |= RG_FLAG_NONFINITE;
+            break;
+        }
+        // Rank test (Section 3): dependent iff ||Gamma_r|| < eps or < eps ||Gamma||.
+        const double eps = eps_in < 0.0 ? ((double)m * m * r + (double)m * r + m) * DBL_EPSILON : eps_in;
+        const double nr = sqrt(s), ng = sqrt(g2);
+        const bool indep = !(nr < eps || nr < eps * ng);
+        if (indep && r == rmax) {
+            fl |= RG_FLAG_RANK_CAPACITY;
+            break;
+        }
+        const double dy = y - gx;
+        // zeta = P^-1 gamma (P^-1 symmetric: column reads coalesce).
+        for (int a = tid; a < r; a += NT) {
+            double acc = 0.0;
+            for (int k = 0; k < r; ++k) acc += P[(size_t)k * rmax + a] * sg[k];
+            sz[a] = acc;
+        }
+        __syncthreads();
+        // beta = B zeta over the i rows so far.
+        for (int t = tid; t < i; t += NT) {
+            double acc = 0.0;
+            const double *brow = Bf + (size_t)t * rmax;
+            for (int k = 0; k < r; ++k) acc += brow[k] * sz[k];
+            beta[t] = acc;
+        }
+        double den = 1.0;
+        if (!indep) {
+            double gz = 0.0, u0 = 0.0, u1 = 0.0;
+            for (int a = tid; a < r; a += NT) gz += sg[a] * sz[a];
+            block_sum3(gz, u0, u1, red);
+            den = 1.0 + gz;
+            if (!(den > 0.0) || !isfinite(den)) {
+                fl |= RG_FLAG_DENOMINATOR;
+                break;
+            }
+        }
+        for (int j = tid; j < m; j += NT) {
+            double kj;
+            if (indep) {
+                kj = sR[j] / s;
+            } else {
+                double acc = 0.0;
+                for (int k = 0; k < r; ++k) acc += Ct[(size_t)k * m + j] * sz[k];
+                kj = acc / den;
+            }
+            sK[j] = kj;
+        }
+        __syncthreads();  // K and beta complete
+        // A^+ <- [A^+ - K beta^T, K]: one wave per row j, lanes over columns.
+        for (int j = wid; j < m; j += NW) {
+            const double kj = sK[j];
+            double *arow = Apb + (size_t)j * n;
+            for (int c = lane; c < i; c += 64) arow[c] -= kj * beta[c];
+            if (lane == 0) arow[i] = kj;
+        }
+        for (int j = tid; j < m; j += NT) Xb[j] += sK[j] * dy;
+        if (indep) {
+            for (int k = wid; k < r; k += NW)
+                for (int j = lane; j < m; j += 64) Ct[(size_t)k * m + j] -= sg[k] * sK[j];
+            for (int j = tid; j < m; j += NT) {
+                Ct[(size_t)r * m + j] = sK[j];
+                C[(size_t)r * m + j] = sG[j];
+            }
+            if (tid == 0) {
+                P[(size_t)r * rmax + r] = 1.0;
+                Bf[(size_t)i * rmax + r] = 1.0;
+            }
+            r += 1;
+        } else {
+            for (int a = wid; a < r; a += NW)
+                for (int k = lane; k < r; k += 64) P[(size_t)a * rmax + k] -= sz[a] * sz[k] / den;
+            for (int k = tid; k < r; k += NT) Bf[(size_t)i * rmax + k] = sg[k];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        rank[b] = r;
+        flags[b] = fl;
+    }
+}
+
+size_t lds_bytes(int m, int rmax) { return sizeof(double) * (3 * (size_t)m + 2 * (size_t)rmax + 3 * NW); }
+
+}  // namespace
+
+extern "C" size_t rg_pinv_track_workspace_bytes(int32_t B, int32_t n, int32_t m, int32_t r_max) {
+    if (B < 1 || n < 0 || m < 1 || r_max < 1 || r_max > m) return 0;
+    return sizeof(double) * (size_t)B * per_problem(n, m, r_max);
+}
+
+extern "C" rg_status rg_pinv_track(const double *A, const double *Y, int32_t B, int32_t n, int32_t m,
+                                   int32_t r_max, double eps, double *Ap, double *X, int32_t *rank,
+                                   uint32_t *flags, void *work, size_t work_bytes, void *stream) {
+    if (B < 1 || n < 0 || m < 1 || r_max < 1 || r_max > m || std::isnan(eps)) return RG_E_INVALID;
+    if (!X || !rank || !flags || !work) return RG_E_INVALID;
+    if (n > 0 && (!A || !Y || !Ap)) return RG_E_INVALID;
+    if (work_bytes < rg_pinv_track_workspace_bytes(B, n, m, r_max)) return RG_E_INVALID;
+    const size_t lds = lds_bytes(m, r_max);
+    if (lds > 160 * 1024) return RG_E_UNSUPPORTED;
+    hipLaunchKernelGGL(k_pinv_track, dim3(B), dim3(NT), lds, (hipStream_t)stream, A, Y, n, m, r_max, eps, Ap, X,
+                       rank, flags, (double *)work, per_problem(n, m, r_max));
+    return hipGetLastError() == hipSuccess ? RG_OK : RG_E_DEVICE;
+}

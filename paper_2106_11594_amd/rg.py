@@ -63,6 +63,9 @@ _SIGS = {
     "rg_class_fits": (ctypes.c_int, [_i32, _i32, _i32, _p]),
     "rg_set_class_rules": (ctypes.c_int, [_p, _p, _p, _i32]),
     "rg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "rg_pinv_track_workspace_bytes": (ctypes.c_size_t, [_i32, _i32, _i32, _i32]),
+    "rg_pinv_track": (ctypes.c_int, [_p, _p, _i32, _i32, _i32, _i32, ctypes.c_double, _p, _p, _p, _p, _p,
+                                     ctypes.c_size_t, _p]),
 }
 
 
@@ -354,6 +357,49 @@ def rg_solve(A, Y, eps=None, r_max=None):
 
 
 # ---- kernel size classes ------------------------------------------------------
+
+def pinv_track_workspace_bytes(B, n, m, r_max):
+    """Device bytes rg_pinv_track needs for B problems of n x m with capacity r_max."""
+    return int(lib().rg_pinv_track_workspace_bytes(B, n, m, r_max))
+
+
+def pinv_track(A, Y, r_max=None, eps=None, stream=None):
+    """Theorems 2 and 3: push every row of A (B x n x m, or n x m) with targets
+    Y (B x n, or n) and maintain A^+ row by row (FP64, CUDA tensors).
+    Returns (Ap [B x m x n], X [B x m], rank [B] int32, flags [B] int32), with
+    the batch dimension dropped for a 2-D A.  r_max defaults to min(n, m);
+    eps=None takes the default threshold of Section 3."""
+    torch = _torch()
+    squeeze = A.dim() == 2
+    if squeeze:
+        A, Y = A.unsqueeze(0), Y.unsqueeze(0)
+    if A.dim() != 3 or Y.shape != A.shape[:2]:
+        raise ValueError("A must be B x n x m and Y B x n")
+    B, n, m = A.shape
+    if r_max is None:
+        r_max = max(1, min(n, m))
+    dev = A.device
+    Ap = torch.empty((B, m, n), dtype=torch.float64, device=dev)
+    X = torch.empty((B, m), dtype=torch.float64, device=dev)
+    rank = torch.empty(B, dtype=torch.int32, device=dev)
+    flags = torch.empty(B, dtype=torch.int32, device=dev)
+    nbytes = pinv_track_workspace_bytes(B, n, m, r_max)
+    if nbytes == 0:
+        raise RGError(1, "rg_pinv_track_workspace_bytes")
+    work = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    null = ctypes.c_void_p(0)
+    _check(lib().rg_pinv_track(_dev(A, torch.float64, "A") if n else null,
+                               _dev(Y, torch.float64, "Y") if n else null, B, n, m, r_max,
+                               -1.0 if eps is None else float(eps),
+                               _dev(Ap, None, "Ap") if n else null, _dev(X, None, "X"), _dev(rank, None, "rank"),
+                               _dev(flags, None, "flags"), _dev(work, None, "work"), nbytes,
+                               ctypes.c_void_p(stream.cuda_stream)), "rg_pinv_track")
+    if squeeze:
+        return Ap[0], X[0], rank[0], flags[0]
+    return Ap, X, rank, flags
+
 
 def class_count():
     """Number of on-chip kernel classes for FP32 streams (rg_class_count)."""

@@ -82,3 +82,21 @@ def test_both_variant_bits_are_rejected_before_the_device(L):
     o.flags = rg.OPT_ORTHOGONAL | rg.OPT_ORTHONORMAL
     h = ctypes.c_void_p()
     assert L.rg_init(ctypes.byref(h), 8, ctypes.byref(o)) == 1
+
+
+def test_pinv_track_rejects_invalid_arguments_before_the_device(L):
+    f = L.rg_pinv_track
+    nb = L.rg_pinv_track_workspace_bytes
+    assert nb(2, 10, 6, 3) == 8 * 2 * (2 * 3 * 6 + 3 * 3 + 10 * 3 + 10)
+    assert nb(0, 10, 6, 3) == 0 and nb(1, 10, 6, 7) == 0 and nb(1, -1, 6, 3) == 0
+    dummy = ctypes.c_void_p(16)
+    args = lambda B, n, m, r, eps, work, wb: (dummy, dummy, B, n, m, r, eps, dummy, dummy, dummy, dummy,
+                                               work, wb, None)
+    big = 1 << 30
+    assert f(*args(0, 10, 6, 3, -1.0, dummy, big)) == 1          # no problems
+    assert f(*args(1, 10, 6, 7, -1.0, dummy, big)) == 1          # r_max > m
+    assert f(*args(1, 10, 6, 3, float("nan"), dummy, big)) == 1  # NaN threshold
+    assert f(*args(1, 10, 6, 3, -1.0, None, big)) == 1           # no workspace
+    assert f(*args(1, 10, 6, 3, -1.0, dummy, 8)) == 1            # workspace too small
+    assert f(None, None, 1, 10, 6, 3, -1.0, None, dummy, dummy, dummy, dummy, big, None) == 1
+    assert f(*args(1, 10, 30000, 3, -1.0, dummy, big)) == 4      # LDS beyond 160 KiB
