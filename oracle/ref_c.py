@@ -28,13 +28,41 @@ def build():
     return _LIB
 
 
-def load():
+def build_from_source(src_text, out_path):
+    """Compile C oracle source text (e.g. a copy with a mistake planted by a
+    mutation test) into ``out_path``; returns the path."""
+    src = out_path + ".c"
+    with open(src, "w") as f:
+        f.write(src_text)
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread", src, "-o", out_path, "-lm"])
+    return out_path
+
+
+def source():
+    with open(_SRC) as f:
+        return f.read()
+
+
+_other = {}
+
+
+def load(lib_path=None):
+    """Load the oracle library (``lib_path``: another build of the same source,
+    such as a mutated copy)."""
     global _lib
+    if lib_path is not None:
+        if lib_path not in _other:
+            _other[lib_path] = _bind(ctypes.CDLL(lib_path))
+        return _other[lib_path]
     if _lib is not None:
         return _lib
     if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         build()
-    lib = ctypes.CDLL(_LIB)
+    _lib = _bind(ctypes.CDLL(_LIB))
+    return _lib
+
+
+def _bind(lib):
     lib.rgo_new.restype = _p
     lib.rgo_new.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double]
     lib.rgo_free.argtypes = [_p]
@@ -46,7 +74,6 @@ def load():
     lib.rgo_solve_batch.restype = ctypes.c_int
     lib.rgo_solve_batch.argtypes = [ctypes.c_int, _p, _p, _p, _p, _p, _p, ctypes.c_double, _p, _p, _p, _p, _p,
                                     ctypes.c_int]
-    _lib = lib
     return lib
 
 
@@ -57,8 +84,8 @@ def _ptr(a):
 class Stream:
     """One recursive least-squares stream kept by the C oracle."""
 
-    def __init__(self, m, cap=None, eps=-1.0):
-        self._lib = load()
+    def __init__(self, m, cap=None, eps=-1.0, lib_path=None):
+        self._lib = load(lib_path)
         self.m = int(m)
         self.cap = int(cap if cap is not None else m)
         self._h = self._lib.rgo_new(self.m, self.cap, float(eps))
@@ -104,10 +131,10 @@ class Stream:
             pass
 
 
-def solve(A, Y, eps=-1.0, cap=None, decisions=False):
+def solve(A, Y, eps=-1.0, cap=None, decisions=False, lib_path=None):
     """Solve one stream from scratch; returns (x, r, C, Ct, Pinv[, decisions])."""
     A = np.asarray(A, dtype=np.float64)
-    s = Stream(A.shape[1], cap, eps)
+    s = Stream(A.shape[1], cap, eps, lib_path)
     dec = s.push(A, Y, decisions)
     X, C, Ct, P = s.state()
     r = s.rank

@@ -14,6 +14,8 @@ from fractions import Fraction as F
 import pytest
 
 from oracle import rg_ref
+from oracle import ref_c
+from tests import test_oracle_rank_test as R
 from tests.test_oracle_exact import _planted
 
 MUTATIONS = {
@@ -28,6 +30,20 @@ MUTATIONS = {
     "pinv_border_two": ("[[z] * r + [z + 1]]", "[[z] * r + [z + 2]]"),
     "basis_stores_rejection": ("st.C.append(list(Gamma))", "st.C.append(list(Gamma_r))"),
     "gain_dependent_no_den": ("for k in range(r)), z) / den for j", "for k in range(r)), z) for j"),
+    # the relative clause of the rank test (Section 3), float and rational branches
+    "rank_rel_dropped": ("return nr < eps or nr < eps * ng", "return nr < eps"),
+    "rank_rel_squared": ("return nr < eps or nr < eps * ng", "return nr < eps or nr < eps * ng * ng"),
+    "rank_rel_not_strict": ("return nr < eps or nr < eps * ng", "return nr < eps or nr <= eps * ng"),
+    "rank_rel_dropped_exact": ("return s < e2 or s < e2 * g", "return s < e2"),
+    "rank_rel_squared_exact": ("return s < e2 or s < e2 * g", "return s < e2 or s < e2 * g * g"),
+    "rank_rel_not_strict_exact": ("return s < e2 or s < e2 * g", "return s < e2 or s <= e2 * g"),
+}
+
+# The same three slips planted in the C oracle's rank test.
+C_MUTATIONS = {
+    "c_rank_rel_dropped": ("(nr < eps) || (nr < eps * ng)", "(nr < eps)"),
+    "c_rank_rel_squared": ("(nr < eps) || (nr < eps * ng)", "(nr < eps) || (nr < eps * ng * ng)"),
+    "c_rank_rel_not_strict": ("(nr < eps) || (nr < eps * ng)", "(nr < eps) || (nr <= eps * ng)"),
 }
 
 
@@ -41,6 +57,9 @@ def _mutant(old, new):
 
 def _pins_pass(mod):
     """A subset of the oracle pins, run against module ``mod``."""
+    for rows, eps, want in R.CASES.values():
+        if R.python_float_decisions(mod, rows, eps) != want or R.python_exact_decisions(mod, rows, eps) != want:
+            return False
     gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "worked_example_m2.json")))
     st = mod.RGState(2, F(0))
     for row, y in zip(gold["rows"], gold["y"]):
@@ -70,3 +89,20 @@ def test_unmutated_passes():
 def test_mutation_is_caught(name):
     old, new = MUTATIONS[name]
     assert not _pins_pass(_mutant(old, new))
+
+
+def _c_pins_pass(lib_path):
+    return all(R.c_decisions(rows, eps, lib_path) == want for rows, eps, want in R.CASES.values())
+
+
+def test_c_unmutated_passes(tmp_path):
+    assert _c_pins_pass(ref_c.build_from_source(ref_c.source(), str(tmp_path / "librg_ref_copy.so")))
+
+
+@pytest.mark.parametrize("name", sorted(C_MUTATIONS))
+def test_c_mutation_is_caught(name, tmp_path):
+    old, new = C_MUTATIONS[name]
+    src = ref_c.source()
+    assert src.count(old) == 1, old
+    lib = ref_c.build_from_source(src.replace(old, new), str(tmp_path / ("librg_ref_%s.so" % name)))
+    assert not _c_pins_pass(lib)
