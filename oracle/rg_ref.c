@@ -88,7 +88,9 @@ static int rgo_update(rgo_state *s, const double *G, double y)
     double eps = s->eps;
     if (eps < 0.0) eps = ((double)m * m * r + (double)m * r + m) * 0x1p-52;
     const double nr = sqrt(nr2), ng = sqrt(ng2);
-    const int dependent = (nr < eps) || (nr < eps * ng);
+    /* an exactly zero rejection is dependent for every eps: with eps = 0 this
+     * is Algorithm 1's exact test Gamma_r == 0 (the Python oracle's eps = 0) */
+    const int dependent = (nr2 == 0.0) || (nr < eps) || (nr < eps * ng);
 
     double dy = y;                                /* a priori residual */
     for (int j = 0; j < m; ++j) dy -= G[j] * X[j];
