@@ -26,9 +26,12 @@
  *  - Errors: invalid arguments return RG_E_INVALID and leave the state
  *    untouched.  Conditions found on the device while rows are applied set a
  *    sticky per-stream flag (RG_FLAG_*): that row and every later row of that
- *    stream are ignored until rg_reset.  Pushes return RG_OK once the work is
- *    enqueued; read the flags to learn what happened.  No C++ exception
- *    crosses this boundary.
+ *    stream are ignored until rg_reset.  Pushes are asynchronous and return
+ *    RG_OK once the work is enqueued, except that rg_push_rows returns
+ *    RG_E_STATE (enqueueing nothing) once a synchronising call on the handle
+ *    (rg_rank, rg_status_flags, rg_check, rg_batch_*) has seen the stream
+ *    flagged.  rg_check / rg_batch_status map the flags to status codes.  No
+ *    C++ exception crosses this boundary.
  *  - Element types: RG_F32 streams take float rows/targets and keep C and Ct
  *    in FP32, P^-1 in FP64 (FP32 Sherman-Morrison downdates lose positive
  *    definiteness on ill-conditioned bases), and the rejection, its norm, the
@@ -47,10 +50,15 @@ extern "C" {
 
 typedef enum {
     RG_OK = 0,
-    RG_E_INVALID = 1,       /* bad argument; nothing was done */
-    RG_E_NOMEM = 2,         /* device or host allocation failed (init only) */
-    RG_E_DEVICE = 3,        /* a HIP runtime call failed */
-    RG_E_UNSUPPORTED = 4    /* valid request outside the library's limits */
+    RG_E_INVALID = 1,        /* bad argument; nothing was done */
+    RG_E_NOMEM = 2,          /* device or host allocation failed (init only) */
+    RG_E_DEVICE = 3,         /* a HIP runtime call failed */
+    RG_E_RANK_CAPACITY = 4,  /* the stream holds RG_FLAG_RANK_CAPACITY */
+    RG_E_NONFINITE = 5,      /* the stream holds RG_FLAG_NONFINITE */
+    RG_E_STATE = 6,          /* the stream is flagged (for a push: flagged streams
+                                take no rows until rg_reset; from rg_check: it
+                                holds RG_FLAG_DENOMINATOR) */
+    RG_E_UNSUPPORTED = 7     /* valid request outside the library's limits */
 } rg_status;
 
 typedef enum { RG_F32 = 0, RG_F64 = 1 } rg_dtype;
@@ -115,6 +123,12 @@ rg_status rg_rank(rg_handle h, int32_t *r);
 /* Sticky RG_FLAG_* bits (host).  Synchronises the handle's stream. */
 rg_status rg_status_flags(rg_handle h, uint32_t *flags);
 
+/* Synchronise the handle's stream and return the stream's condition as a
+ * status: RG_OK (no flag), RG_E_NONFINITE, RG_E_RANK_CAPACITY or RG_E_STATE
+ * (RG_FLAG_DENOMINATOR), in that order of precedence when several flags are
+ * set.  Single-stream handles only (RG_E_INVALID otherwise). */
+rg_status rg_check(rg_handle h);
+
 /* Back to the empty state (rank 0, x = 0, flags cleared); stream-ordered. */
 rg_status rg_reset(rg_handle h);
 
@@ -128,6 +142,30 @@ rg_status rg_destroy(rg_handle h);
  * Streams are numbered 0..B-1 everywhere below. */
 rg_status rg_batch_init(rg_handle *out, int32_t B, const int32_t *m, const int32_t *r_max,
                         const rg_options *opt);
+
+/* rg_batch_init on a workspace the caller provides: ws (device, at least
+ * rg_workspace_bytes(B, m, r_max, opt->dtype) bytes, 256-byte aligned) holds
+ * all device state of the handle, and the library allocates no device memory
+ * for it; the caller keeps ws valid until rg_destroy, which does not free it.
+ * ws_bytes smaller than needed or a misaligned ws is RG_E_INVALID.  The
+ * handle itself (host) and, for batches whose streams fall into two or more
+ * kernel classes, its auxiliary HIP streams and events are still created. */
+rg_status rg_batch_init_ws(rg_handle *out, int32_t B, const int32_t *m, const int32_t *r_max,
+                           const rg_options *opt, void *ws, size_t ws_bytes);
+
+/* Check a packed row layout on the host before it is pushed: copies row_ptr
+ * (device, B+1) and gamma_off (device, B) to the host (synchronising the
+ * handle's stream) and returns RG_E_INVALID unless row_ptr starts at 0, never
+ * decreases and ends at n_rows (the length of y), and every stream's rows
+ * [gamma_off[b], gamma_off[b] + n_b m_b) lie inside [0, n_elems) (the length
+ * of gamma) without overlapping another stream's.  rg_batch_push itself does
+ * not read these arrays on the host. */
+rg_status rg_batch_check_layout(rg_handle h, const int64_t *row_ptr, const int64_t *gamma_off, int64_t n_rows,
+                                int64_t n_elems);
+
+/* Per-stream condition (host, B rg_status values, as rg_check gives for one
+ * stream).  Synchronises. */
+rg_status rg_batch_status(rg_handle h, int32_t *status);
 
 /* Push rows to every stream at once.  Stream b receives the rows
  * row_ptr[b] .. row_ptr[b+1]-1 of the packed target vector y (device), and

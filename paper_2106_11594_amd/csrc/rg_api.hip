@@ -24,6 +24,8 @@ struct rg_ctx {
     int num_cus = 0;
     void *ws = nullptr;          // one device allocation for everything below
     size_t ws_bytes = 0;
+    bool own_ws = true;          // false: the caller provided ws (rg_batch_init_ws)
+    uint32_t known_flags = 0;    // OR of the stream flags the last synchronising call read
     StreamMeta *d_meta = nullptr;
     int32_t *d_order = nullptr;  // B entries: generic-class streams first, then each size class
     uint32_t *d_counter = nullptr;  // one queue head per kernel family (RG_MAX_FAMILIES)
@@ -159,22 +161,32 @@ rg_status push_impl(rg_ctx *h, const void *gamma, const void *y, const int64_t *
     for (int f = 1; f < RG_MAX_FAMILIES; ++f) nact += h->fam_count[f] > 0;
     const bool serial = (h->opts & RG_OPT_SERIAL_CLASSES) != 0 || nact < 2;
     if (nact > 0 && !serial) HIPCHK(hipEventRecord(h->fork, h->stream));
-    for (int f = RG_MAX_FAMILIES - 1; f >= 1; --f) {
+    // Every family that was forked is joined back, also when a later launch
+    // fails, so that the handle's stream always covers all work of the push.
+    bool forked[RG_MAX_FAMILIES] = {};
+    hipError_t err = hipSuccess;
+    for (int f = RG_MAX_FAMILIES - 1; f >= 1 && err == hipSuccess; --f) {
         if (h->fam_count[f] == 0) continue;
         a.order = h->d_order + h->fam_begin[f];
         a.n_order = h->fam_count[f];
         a.counter = h->d_counter + f;
         if (serial) {
-            HIPCHK(rg::launch_push_class<T>(f - 1, a, h->fam_rows[f], h->stream));
+            err = rg::launch_push_class<T>(f - 1, a, h->fam_rows[f], h->stream);
             continue;
         }
-        HIPCHK(hipStreamWaitEvent(h->aux[f], h->fork, 0));
-        HIPCHK(rg::launch_push_class<T>(f - 1, a, h->fam_rows[f], h->aux[f]));
-        HIPCHK(hipEventRecord(h->join[f], h->aux[f]));
+        err = hipStreamWaitEvent(h->aux[f], h->fork, 0);
+        if (err != hipSuccess) break;
+        forked[f] = true;
+        err = rg::launch_push_class<T>(f - 1, a, h->fam_rows[f], h->aux[f]);
     }
-    if (!serial)
-        for (int f = 1; f < RG_MAX_FAMILIES; ++f)
-            if (h->fam_count[f] > 0) HIPCHK(hipStreamWaitEvent(h->stream, h->join[f], 0));
+    for (int f = 1; f < RG_MAX_FAMILIES; ++f) {
+        if (!forked[f]) continue;
+        hipError_t e = hipEventRecord(h->join[f], h->aux[f]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(h->stream, h->join[f], 0);
+        if (e != hipSuccess) (void)hipStreamSynchronize(h->aux[f]);
+        if (err == hipSuccess) err = e;
+    }
+    if (err != hipSuccess) return RG_E_DEVICE;
     if (h->fam_count[0] > 0 && h->d_big && !row_ptr) {
         const StreamMeta &M = h->h_meta[0];
         HIPCHK(rg::launch_push_big<T>(a, h->d_big, M.m, M.r_max, h->num_cus, h->stream));
@@ -191,6 +203,25 @@ rg_status push_impl(rg_ctx *h, const void *gamma, const void *y, const int64_t *
 }
 
 bool valid_handle(rg_handle h) { return h != nullptr && h->ws != nullptr; }
+
+// Status of one stream's sticky flags (precedence: non-finite input, rank
+// capacity, denominator).
+rg_status flag_status(uint32_t f) {
+    if (f & RG_FLAG_NONFINITE) return RG_E_NONFINITE;
+    if (f & RG_FLAG_RANK_CAPACITY) return RG_E_RANK_CAPACITY;
+    if (f) return RG_E_STATE;
+    return RG_OK;
+}
+
+// Wait for every stream the handle enqueues on (its own and the forked class
+// streams), so that nothing of it runs any more.
+rg_status drain(rg_ctx *h) {
+    rg_status st = RG_OK;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) st = RG_E_DEVICE;
+    for (int f = 0; f < RG_MAX_FAMILIES; ++f)
+        if (h->aux[f] && hipStreamSynchronize(h->aux[f]) != hipSuccess) st = RG_E_DEVICE;
+    return st;
+}
 
 void release_streams(rg_ctx *h) {
     for (int f = 0; f < RG_MAX_FAMILIES; ++f) {
@@ -222,6 +253,9 @@ const char *rg_status_string(rg_status s) {
         case RG_E_INVALID: return "invalid argument";
         case RG_E_NOMEM: return "out of memory";
         case RG_E_DEVICE: return "HIP runtime error";
+        case RG_E_RANK_CAPACITY: return "rank capacity reached";
+        case RG_E_NONFINITE: return "non-finite row or target";
+        case RG_E_STATE: return "stream is flagged";
         case RG_E_UNSUPPORTED: return "unsupported size";
     }
     return "unknown status";
@@ -262,7 +296,8 @@ size_t rg_workspace_bytes(int32_t B, const int32_t *m, const int32_t *r_max, int
     return ws_size(L, B, es, big ? rg::big_scratch_doubles(M0.m, M0.r_max) : 0);
 }
 
-rg_status rg_batch_init(rg_handle *out, int32_t B, const int32_t *m, const int32_t *r_max, const rg_options *opt) {
+static rg_status batch_init(rg_handle *out, int32_t B, const int32_t *m, const int32_t *r_max,
+                            const rg_options *opt, void *user_ws, size_t user_bytes) {
     if (!out) return RG_E_INVALID;
     *out = nullptr;
     if (B <= 0 || !m) return RG_E_INVALID;
@@ -314,7 +349,14 @@ rg_status rg_batch_init(rg_handle *out, int32_t B, const int32_t *m, const int32
                      !(o.flags & (RG_OPT_GENERIC_KERNEL | RG_OPT_ORTHOGONAL | RG_OPT_ORTHONORMAL));
     const size_t big_doubles = big ? rg::big_scratch_doubles(M0.m, M0.r_max) : 0;
     h->ws_bytes = ws_size(L, B, h->esize, big_doubles);
-    if (hipMalloc(&h->ws, h->ws_bytes) != hipSuccess) {
+    if (user_ws) {
+        if (user_bytes < h->ws_bytes || ((uintptr_t)user_ws & 255u) != 0) {
+            delete h;
+            return RG_E_INVALID;
+        }
+        h->ws = user_ws;
+        h->own_ws = false;
+    } else if (hipMalloc(&h->ws, h->ws_bytes) != hipSuccess) {
         h->ws = nullptr;
         delete h;
         return RG_E_NOMEM;
@@ -342,13 +384,27 @@ rg_status rg_batch_init(rg_handle *out, int32_t B, const int32_t *m, const int32
     for (int b = 0; b < B; ++b) h->cost[b] = (int64_t)h->h_meta[b].m * h->h_meta[b].m * h->h_meta[b].r_max;
     if (st == RG_OK) st = upload_order(h);
     if (st != RG_OK) {
-        (void)hipFree(h->ws);
+        (void)drain(h);
         release_streams(h);
+        if (h->own_ws) (void)hipFree(h->ws);
         delete h;
         return st;
     }
     *out = h;
     return RG_OK;
+}
+
+rg_status rg_batch_init(rg_handle *out, int32_t B, const int32_t *m, const int32_t *r_max, const rg_options *opt) {
+    return batch_init(out, B, m, r_max, opt, nullptr, 0);
+}
+
+rg_status rg_batch_init_ws(rg_handle *out, int32_t B, const int32_t *m, const int32_t *r_max,
+                           const rg_options *opt, void *ws, size_t ws_bytes) {
+    if (!ws) {
+        if (out) *out = nullptr;
+        return RG_E_INVALID;
+    }
+    return batch_init(out, B, m, r_max, opt, ws, ws_bytes);
 }
 
 rg_status rg_init(rg_handle *out, int32_t m, const rg_options *opt) {
@@ -377,6 +433,7 @@ rg_status rg_push_rows(rg_handle h, const void *gamma, const void *y, int64_t k)
     if (!valid_handle(h) || h->B != 1 || k < 0) return RG_E_INVALID;
     if (k == 0) return RG_OK;
     if (!gamma || !y) return RG_E_INVALID;
+    if (h->known_flags) return RG_E_STATE;
     return h->dtype == RG_F64 ? push_impl<double>(h, gamma, y, nullptr, nullptr, k)
                               : push_impl<float>(h, gamma, y, nullptr, nullptr, k);
 }
@@ -407,6 +464,9 @@ static rg_status read_meta(rg_handle h, std::vector<StreamMeta> &dst) {
     dst.resize(h->B);
     HIPCHK(hipMemcpyAsync(dst.data(), h->d_meta, sizeof(StreamMeta) * h->B, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
+    uint32_t any = 0;
+    for (int b = 0; b < h->B; ++b) any |= dst[b].flags;
+    h->known_flags = any;
     return RG_OK;
 }
 
@@ -440,7 +500,50 @@ rg_status rg_status_flags(rg_handle h, uint32_t *flags) {
 
 rg_status rg_reset(rg_handle h) {
     if (!valid_handle(h)) return RG_E_INVALID;
-    return rg::launch_reset_streams(h->d_meta, h->B, h->stream) == hipSuccess ? RG_OK : RG_E_DEVICE;
+    if (rg::launch_reset_streams(h->d_meta, h->B, h->stream) != hipSuccess) return RG_E_DEVICE;
+    h->known_flags = 0;
+    return RG_OK;
+}
+
+rg_status rg_check(rg_handle h) {
+    if (!valid_handle(h) || h->B != 1) return RG_E_INVALID;
+    std::vector<StreamMeta> M;
+    rg_status st = read_meta(h, M);
+    return st != RG_OK ? st : flag_status(M[0].flags);
+}
+
+rg_status rg_batch_status(rg_handle h, int32_t *status) {
+    if (!valid_handle(h) || !status) return RG_E_INVALID;
+    std::vector<StreamMeta> M;
+    rg_status st = read_meta(h, M);
+    if (st != RG_OK) return st;
+    for (int b = 0; b < h->B; ++b) status[b] = (int32_t)flag_status(M[b].flags);
+    return RG_OK;
+}
+
+rg_status rg_batch_check_layout(rg_handle h, const int64_t *row_ptr, const int64_t *gamma_off, int64_t n_rows,
+                                int64_t n_elems) {
+    if (!valid_handle(h) || !row_ptr || !gamma_off || n_rows < 0 || n_elems < 0) return RG_E_INVALID;
+    const int B = h->B;
+    std::vector<int64_t> rp(B + 1), go(B);
+    HIPCHK(hipMemcpyAsync(rp.data(), row_ptr, sizeof(int64_t) * (B + 1), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(go.data(), gamma_off, sizeof(int64_t) * B, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    if (rp[0] != 0 || rp[B] != n_rows) return RG_E_INVALID;
+    std::vector<std::pair<int64_t, int64_t>> spans;
+    spans.reserve(B);
+    for (int b = 0; b < B; ++b) {
+        const int64_t nb = rp[b + 1] - rp[b];
+        if (nb < 0) return RG_E_INVALID;
+        if (nb == 0) continue;
+        const int64_t len = nb * (int64_t)h->h_meta[b].m;
+        if (go[b] < 0 || go[b] > n_elems - len) return RG_E_INVALID;
+        spans.push_back({go[b], go[b] + len});
+    }
+    std::sort(spans.begin(), spans.end());
+    for (size_t k = 1; k < spans.size(); ++k)
+        if (spans[k].first < spans[k - 1].second) return RG_E_INVALID;
+    return RG_OK;
 }
 
 rg_status rg_batch_get_state(rg_handle h, int32_t b, void *C, void *Ct, void *Pinv, double *w) {
@@ -492,14 +595,15 @@ rg_status rg_batch_pinv(rg_handle h, const void *A, const int64_t *row_ptr, cons
     return e == hipSuccess ? RG_OK : RG_E_DEVICE;
 }
 
+// Teardown order: wait for every stream the handle used (its own and the
+// forked class streams), destroy those streams and events, and only then free
+// the workspace, so that no enqueued kernel or event can outlive the memory.
 rg_status rg_destroy(rg_handle h) {
     if (!h) return RG_E_INVALID;
-    rg_status st = RG_OK;
-    if (h->ws) {
-        if (hipStreamSynchronize(h->stream) != hipSuccess) st = RG_E_DEVICE;
-        if (hipFree(h->ws) != hipSuccess) st = RG_E_DEVICE;
-    }
+    rg_status st = drain(h);
     release_streams(h);
+    if (h->ws && h->own_ws && hipFree(h->ws) != hipSuccess) st = RG_E_DEVICE;
+    h->ws = nullptr;
     delete h;
     return st;
 }

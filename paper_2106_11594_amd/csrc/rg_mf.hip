@@ -1257,12 +1257,18 @@ template <class K>
 bool fits_k(int m, int r_max) {
     return m <= K::MMAX && r_max <= K::RMAX && lds_bytes<K>(rows16(r_max)) <= 160 * 1024;
 }
+// Set once per variant, to the LDS the variant needs at its full rank
+// capacity (the limit is process-wide: a later handle must not lower it under
+// the launches of a live one).
 template <class K>
 hipError_t prepare_k(int r_max) {
-    const size_t lds = lds_bytes<K>(rows16(r_max));
-    if (lds > 160 * 1024) return hipErrorInvalidValue;
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_push_mf<K>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (lds_bytes<K>(rows16(r_max)) > 160 * 1024) return hipErrorInvalidValue;
+    static_assert(sizeof(float) * K::RMAX * K::MMAX + sizeof(double) * (K::X1_D + K::X2_D) <= 160 * 1024,
+                  "every variant fits the LDS at its full capacity");
+    static const hipError_t once = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_push_mf<K>),
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                       (int)lds_bytes<K>(K::RMAX));
+    return once;
 }
 template <class K>
 hipError_t launch_k(const PushArgs<float> &a, int r_max, hipStream_t s) {

@@ -115,10 +115,12 @@ __global__ void __launch_bounds__(NT) k_pinv_track(const double *A, const double
             fl |= RG_FLAG_NONFINITE;
             break;
         }
-        // Rank test (Section 3): dependent iff ||Gamma_r|| < eps or < eps ||Gamma||.
+        // Rank test (Section 3): dependent iff ||Gamma_r|| < eps or < eps ||Gamma||;
+        // an exactly zero rejection is dependent for every eps (eps = 0 is the
+        // exact test Gamma_r == 0 of Algorithm 1).
         const double eps = eps_in < 0.0 ? ((double)m * m * r + (double)m * r + m) * DBL_EPSILON : eps_in;
         const double nr = sqrt(s), ng = sqrt(g2);
-        const bool indep = !(nr < eps || nr < eps * ng);
+        const bool indep = !(s == 0.0 || nr < eps || nr < eps * ng);
         if (indep && r == rmax) {
             fl |= RG_FLAG_RANK_CAPACITY;
             break;

@@ -489,12 +489,16 @@ bool fits(int m, int r_max) {
     return m <= K::MMAX && r_max <= K::RMAX && lds_bytes<K>(rows_alloc) <= 160 * 1024;
 }
 
+// The dynamic-LDS limit of a class kernel is process-wide state: it is set
+// once, to what the class needs at its full rank capacity, so that a handle
+// created later can never lower it under the launches of a live handle.
 template <class K>
 hipError_t prepare(int rows_alloc) {
-    const size_t lds = lds_bytes<K>(rows_alloc);
-    if (lds > 160 * 1024) return hipErrorInvalidValue;
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_push_rk<K>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (lds_bytes<K>(rows_alloc) > 160 * 1024) return hipErrorInvalidValue;
+    static const hipError_t once = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_push_rk<K>),
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                       (int)lds_bytes<K>(K::RMAX));
+    return once;
 }
 
 template <class K>

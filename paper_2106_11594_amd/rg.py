@@ -20,7 +20,9 @@ FLAG_NONFINITE, FLAG_RANK_CAPACITY, FLAG_DENOMINATOR = 0x1, 0x2, 0x4
 OPT_NO_REPROJECT, OPT_GENERIC_KERNEL, OPT_SERIAL_CLASSES, OPT_ROW_BY_ROW = 0x1, 0x2, 0x4, 0x8
 OPT_DEPENDENT_BLOCKS_ONLY = 0x10
 OPT_ORTHOGONAL, OPT_ORTHONORMAL = 0x20, 0x40
-_STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "HIP runtime error", 4: "unsupported size"}
+OK, E_INVALID, E_NOMEM, E_DEVICE, E_RANK_CAPACITY, E_NONFINITE, E_STATE, E_UNSUPPORTED = range(8)
+_STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "HIP runtime error", 4: "rank capacity reached",
+           5: "non-finite row or target", 6: "stream is flagged", 7: "unsupported size"}
 
 
 class RGError(RuntimeError):
@@ -47,6 +49,10 @@ _SIGS = {
     "rg_rank": (ctypes.c_int, [_p, _p]),
     "rg_status_flags": (ctypes.c_int, [_p, _p]),
     "rg_reset": (ctypes.c_int, [_p]),
+    "rg_check": (ctypes.c_int, [_p]),
+    "rg_batch_init_ws": (ctypes.c_int, [_p, _i32, _p, _p, _p, _p, ctypes.c_size_t]),
+    "rg_batch_check_layout": (ctypes.c_int, [_p, _p, _p, _i64, _i64]),
+    "rg_batch_status": (ctypes.c_int, [_p, _p]),
     "rg_destroy": (ctypes.c_int, [_p]),
     "rg_batch_init": (ctypes.c_int, [_p, _i32, _p, _p, _p]),
     "rg_batch_push": (ctypes.c_int, [_p, _p, _p, _p, _p]),
@@ -129,7 +135,11 @@ def _dev(t, dtype, what, numel=None):
 class Batch:
     """B independent recursive least-squares streams (rg_batch_* calls)."""
 
-    def __init__(self, ms, r_max=None, dtype="f32", eps=None, stream=None, flags=0):
+    def __init__(self, ms, r_max=None, dtype="f32", eps=None, stream=None, flags=0, workspace=None):
+        """workspace: optional caller-owned device tensor (uint8, at least
+        workspace_bytes(ms, r_max, dtype) bytes, 256-byte aligned) that holds
+        the handle's device state instead of a library allocation
+        (rg_batch_init_ws); it must outlive the handle."""
         torch = _torch()
         L = lib()
         self.code, self.tdtype = _dtype_code(dtype)
@@ -151,8 +161,14 @@ class Batch:
         self._opt = opt
         h = ctypes.c_void_p()
         rp = None if self.r_max is None else self.r_max.ctypes.data_as(_p)
-        _check(L.rg_batch_init(ctypes.byref(h), self.B, self.ms.ctypes.data_as(_p), rp, ctypes.byref(opt)),
-               "rg_batch_init")
+        if workspace is None:
+            _check(L.rg_batch_init(ctypes.byref(h), self.B, self.ms.ctypes.data_as(_p), rp, ctypes.byref(opt)),
+                   "rg_batch_init")
+        else:
+            _check(L.rg_batch_init_ws(ctypes.byref(h), self.B, self.ms.ctypes.data_as(_p), rp, ctypes.byref(opt),
+                                      _dev(workspace, None, "workspace"),
+                                      workspace.numel() * workspace.element_size()), "rg_batch_init_ws")
+        self._workspace = workspace
         self._h = h
 
     @property
@@ -185,6 +201,21 @@ class Batch:
         f = np.zeros(self.B, dtype=np.uint32)
         _check(lib().rg_batch_flags(self._h, f.ctypes.data_as(_p)), "rg_batch_flags")
         return f
+
+    def status(self):
+        """Per-stream status codes (rg_batch_status): OK, E_NONFINITE,
+        E_RANK_CAPACITY or E_STATE."""
+        st = np.zeros(self.B, dtype=np.int32)
+        _check(lib().rg_batch_status(self._h, st.ctypes.data_as(_p)), "rg_batch_status")
+        return st
+
+    def check_layout(self, gamma, y, row_ptr, gamma_off):
+        """Host-side check of a packed row layout (rg_batch_check_layout);
+        raises RGError(E_INVALID) when it is inconsistent."""
+        torch = _torch()
+        _check(lib().rg_batch_check_layout(self._h, _dev(row_ptr, torch.int64, "row_ptr", self.B + 1),
+                                           _dev(gamma_off, torch.int64, "gamma_off", self.B),
+                                           int(y.numel()), int(gamma.numel())), "rg_batch_check_layout")
 
     def reset(self):
         _check(lib().rg_reset(self._h), "rg_reset")
@@ -284,6 +315,23 @@ class Solver:
         _check(lib().rg_status_flags(self._h, ctypes.byref(f)), "rg_status_flags")
         return f.value
 
+    def check(self):
+        """rg_check: the stream's condition as a status code (synchronises)."""
+        return int(lib().rg_check(self._h))
+
+    def get_state(self):
+        """(C, Ct, Pinv, w) as device tensors (rank-sized; rg_batch_get_state)."""
+        torch = _torch()
+        r = self.rank()
+        C = torch.empty((r, self.m), dtype=self.tdtype, device="cuda")
+        Ct = torch.empty((r, self.m), dtype=self.tdtype, device="cuda")
+        P = torch.empty((r, r), dtype=torch.float64, device="cuda")
+        w = torch.empty(r, dtype=torch.float64, device="cuda")
+        if r:
+            _check(lib().rg_batch_get_state(self._h, 0, _dev(C, None, "C"), _dev(Ct, None, "Ct"),
+                                            _dev(P, None, "P"), _dev(w, None, "w")), "rg_batch_get_state")
+        return C, Ct, P, w
+
     def reset(self):
         _check(lib().rg_reset(self._h), "rg_reset")
 
@@ -379,16 +427,19 @@ def pinv_track(A, Y, r_max=None, eps=None, stream=None):
     if r_max is None:
         r_max = max(1, min(n, m))
     dev = A.device
-    Ap = torch.empty((B, m, n), dtype=torch.float64, device=dev)
-    X = torch.empty((B, m), dtype=torch.float64, device=dev)
-    rank = torch.empty(B, dtype=torch.int32, device=dev)
-    flags = torch.empty(B, dtype=torch.int32, device=dev)
     nbytes = pinv_track_workspace_bytes(B, n, m, r_max)
     if nbytes == 0:
         raise RGError(1, "rg_pinv_track_workspace_bytes")
-    work = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     if stream is None:
         stream = torch.cuda.current_stream()
+    # outputs and workspace come from the caching allocator on the stream the
+    # kernel runs on, so none of them is reused while the kernel still runs
+    with torch.cuda.stream(stream):
+        Ap = torch.empty((B, m, n), dtype=torch.float64, device=dev)
+        X = torch.empty((B, m), dtype=torch.float64, device=dev)
+        rank = torch.empty(B, dtype=torch.int32, device=dev)
+        flags = torch.empty(B, dtype=torch.int32, device=dev)
+        work = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     null = ctypes.c_void_p(0)
     _check(lib().rg_pinv_track(_dev(A, torch.float64, "A") if n else null,
                                _dev(Y, torch.float64, "Y") if n else null, B, n, m, r_max,

@@ -46,6 +46,23 @@ def test_invalid_arguments_need_no_device(L):
     assert L.rg_rank(None, ctypes.byref(r)) == 1
     assert L.rg_batch_push(None, None, None, None, None) == 1
     assert L.rg_batch_adjoint(None, None, None, None, None, None, None, None) == 1
+    assert L.rg_check(None) == 1
+    assert L.rg_batch_status(None, None) == 1
+    assert L.rg_batch_check_layout(None, None, None, 0, 0) == 1
+    ms = np.array([4, 5], dtype=np.int32)
+    assert L.rg_batch_init_ws(ctypes.byref(h), 2, ms.ctypes.data_as(ctypes.c_void_p), None, None, None, 1 << 20) == 1
+
+
+def test_status_codes_match_the_header():
+    """The rg_status values of include/rg.h equal the binding's constants."""
+    import os
+    import re
+    hdr = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "rg.h")).read()
+    body = hdr.split("typedef enum {", 1)[1].split("} rg_status;", 1)[0]
+    vals = {n: int(v) for n, v in re.findall(r"RG_(\w+)\s*=\s*(\d+)", body)}
+    assert vals == {"OK": rg.OK, "E_INVALID": rg.E_INVALID, "E_NOMEM": rg.E_NOMEM, "E_DEVICE": rg.E_DEVICE,
+                    "E_RANK_CAPACITY": rg.E_RANK_CAPACITY, "E_NONFINITE": rg.E_NONFINITE, "E_STATE": rg.E_STATE,
+                    "E_UNSUPPORTED": rg.E_UNSUPPORTED}
 
 
 def test_default_options(L):
@@ -99,4 +116,4 @@ def test_pinv_track_rejects_invalid_arguments_before_the_device(L):
     assert f(*args(1, 10, 6, 3, -1.0, None, big)) == 1           # no workspace
     assert f(*args(1, 10, 6, 3, -1.0, dummy, 8)) == 1            # workspace too small
     assert f(None, None, 1, 10, 6, 3, -1.0, None, dummy, dummy, dummy, dummy, big, None) == 1
-    assert f(*args(1, 10, 30000, 3, -1.0, dummy, big)) == 4      # LDS beyond 160 KiB
+    assert f(*args(1, 10, 30000, 3, -1.0, dummy, big)) == rg.E_UNSUPPORTED  # LDS beyond 160 KiB

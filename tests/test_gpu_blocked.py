@@ -13,11 +13,7 @@ from oracle import ref_c
 from paper_2106_11594_amd import workloads as W
 
 # (m, r_max) pairs that select each variant of the blocked kernel
-VARIANT_SHAPES = [(100, 44), (120, 100), (170, 60), (190, 120), (250, 40),
-                  pytest.param(256, 128, marks=pytest.mark.skip(
-                      reason="aborted once inside rg_destroy after all results had been read (no GPU fault "
-                             "reported); it had passed in earlier runs of the same build and no cause has been "
-                             "found by reading the code, so it stays off until one is shown"))]
+VARIANT_SHAPES = [(100, 44), (120, 100), (170, 60), (190, 120), (250, 40), (256, 128)]
 
 
 def _rel(x, xo):

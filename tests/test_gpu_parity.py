@@ -60,13 +60,8 @@ def _single(A, Y, dtype, eps=None, r_max=None, chunks=None, flags=0):
 
 def _state(s_or_batch, b=0):
     from paper_2106_11594_amd import rg
-    if isinstance(s_or_batch, rg.Solver):
-        h = rg.Batch.__new__(rg.Batch)
-        h._h, h.ms, h.B, h.tdtype = s_or_batch._h, np.array([s_or_batch.m], np.int32), 1, s_or_batch.tdtype
-        C, Ct, P, w = rg.Batch.get_state(h, b)
-        h._h = None
-        return [t.double().cpu().numpy() for t in (C, Ct, P, w)]
-    return [t.double().cpu().numpy() for t in s_or_batch.get_state(b)]
+    st = s_or_batch.get_state() if isinstance(s_or_batch, rg.Solver) else s_or_batch.get_state(b)
+    return [t.double().cpu().numpy() for t in st]
 
 
 @pytest.mark.parametrize("n", [700, 2000])
