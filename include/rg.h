@@ -254,6 +254,26 @@ rg_status rg_pinv_track(const double *A, const double *Y, int32_t B, int32_t n, 
                         double eps, double *Ap, double *X, int32_t *rank, uint32_t *flags, void *work,
                         size_t work_bytes, void *stream);
 
+/* rg_pinv_track for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same computation and outputs, with the workspace taken from a fixed
+ * device array inside the library instead of a caller buffer.  That array
+ * holds rg_pinv_track_noalloc_max_bytes() bytes (32 MiB) on every GPU the
+ * library runs on, for the life of the process; problems whose
+ * rg_pinv_track_workspace_bytes exceeds it return RG_E_UNSUPPORTED before
+ * any device work.  The call allocates nothing: no hipMalloc, no hipFree.
+ * The caller still passes A, Y and the outputs (device, as for
+ * rg_pinv_track).  Every call on one GPU shares that GPU's array, so calls
+ * that overlap on one GPU (other streams, other threads) race and must be
+ * ordered by the caller; the array's contents on entry do not matter.  The
+ * first call on a device looks up the array's device address (once per
+ * device, with that device current). */
+rg_status rg_pinv_track_noalloc(const double *A, const double *Y, int32_t B, int32_t n, int32_t m, int32_t r_max,
+                                double eps, double *Ap, double *X, int32_t *rank, uint32_t *flags, void *stream);
+
+/* Size in bytes of the fixed device array rg_pinv_track_noalloc works in. */
+size_t rg_pinv_track_noalloc_max_bytes(void);
+
 /* ---- kernel size classes (tuning) -------------------------------------- */
 
 /* FP32 streams run in one of rg_class_count() on-chip kernel classes, or in

@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 #include <cfloat>
 #include <cmath>
+#include <mutex>
 
 namespace {
 
@@ -198,6 +199,35 @@ __global__ void __launch_bounds__(NT) k_pinv_track(const double *A, const double
 
 size_t lds_bytes(int m, int rmax) { return sizeof(double) * (3 * (size_t)m + 2 * (size_t)rmax + 3 * NW); }
 
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(32) << 20;
+
+}  // namespace
+
+// Scratch of rg_pinv_track_noalloc: a file-scope device array, so that entry
+// point needs no allocation.  Every GPU the library runs on holds its own copy
+// for the life of the process.  In host code the array's name is only a host
+// stand-in; its device address, looked up once per device, is what kernels get.
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of this device's scratch array (nullptr on failure); must be
+// called with device dev current.
+void *scratch_address(int dev) {
+    if (dev < 0 || dev >= MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
 }  // namespace
 
 extern "C" size_t rg_pinv_track_workspace_bytes(int32_t B, int32_t n, int32_t m, int32_t r_max) {
@@ -217,4 +247,22 @@ extern "C" rg_status rg_pinv_track(const double *A, const double *Y, int32_t B, 
     hipLaunchKernelGGL(k_pinv_track, dim3(B), dim3(NT), lds, (hipStream_t)stream, A, Y, n, m, r_max, eps, Ap, X,
                        rank, flags, (double *)work, per_problem(n, m, r_max));
     return hipGetLastError() == hipSuccess ? RG_OK : RG_E_DEVICE;
+}
+
+extern "C" size_t rg_pinv_track_noalloc_max_bytes(void) { return NOALLOC_SCRATCH_BYTES; }
+
+extern "C" rg_status rg_pinv_track_noalloc(const double *A, const double *Y, int32_t B, int32_t n, int32_t m,
+                                           int32_t r_max, double eps, double *Ap, double *X, int32_t *rank,
+                                           uint32_t *flags, void *stream) {
+    if (B < 1 || n < 0 || m < 1 || r_max < 1 || r_max > m || std::isnan(eps)) return RG_E_INVALID;
+    if (!X || !rank || !flags) return RG_E_INVALID;
+    if (n > 0 && (!A || !Y || !Ap)) return RG_E_INVALID;
+    const size_t need = rg_pinv_track_workspace_bytes(B, n, m, r_max);
+    if (need > NOALLOC_SCRATCH_BYTES) return RG_E_UNSUPPORTED;
+    if (lds_bytes(m, r_max) > 160 * 1024) return RG_E_UNSUPPORTED;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return RG_E_DEVICE;
+    void *work = scratch_address(dev);
+    if (!work) return RG_E_DEVICE;
+    return rg_pinv_track(A, Y, B, n, m, r_max, eps, Ap, X, rank, flags, work, need, stream);
 }

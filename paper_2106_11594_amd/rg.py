@@ -72,6 +72,9 @@ _SIGS = {
     "rg_pinv_track_workspace_bytes": (ctypes.c_size_t, [_i32, _i32, _i32, _i32]),
     "rg_pinv_track": (ctypes.c_int, [_p, _p, _i32, _i32, _i32, _i32, ctypes.c_double, _p, _p, _p, _p, _p,
                                      ctypes.c_size_t, _p]),
+    "rg_pinv_track_noalloc": (ctypes.c_int, [_p, _p, _i32, _i32, _i32, _i32, ctypes.c_double, _p, _p, _p, _p,
+                                             _p]),
+    "rg_pinv_track_noalloc_max_bytes": (ctypes.c_size_t, []),
 }
 
 
@@ -409,6 +412,31 @@ def rg_solve(A, Y, eps=None, r_max=None):
 def pinv_track_workspace_bytes(B, n, m, r_max):
     """Device bytes rg_pinv_track needs for B problems of n x m with capacity r_max."""
     return int(lib().rg_pinv_track_workspace_bytes(B, n, m, r_max))
+
+
+def pinv_track_noalloc(A, Y, Ap, X, rank, flags, r_max=None, eps=None, stream=None):
+    """rg_pinv_track_noalloc: as pinv_track, into caller-provided outputs
+    (Ap [B x m x n], X [B x m], rank [B], flags [B]; FP64 / int32 CUDA
+    tensors), with the workspace taken from the library's fixed device array:
+    nothing is allocated by the call."""
+    torch = _torch()
+    B, n, m = A.shape
+    if r_max is None:
+        r_max = max(1, min(n, m))
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    null = ctypes.c_void_p(0)
+    _check(lib().rg_pinv_track_noalloc(_dev(A, torch.float64, "A") if n else null,
+                                       _dev(Y, torch.float64, "Y") if n else null, B, n, m, r_max,
+                                       -1.0 if eps is None else float(eps),
+                                       _dev(Ap, torch.float64, "Ap", B * m * n) if n else null,
+                                       _dev(X, torch.float64, "X", B * m), _dev(rank, torch.int32, "rank", B),
+                                       _dev(flags, torch.int32, "flags", B), ctypes.c_void_p(stream.cuda_stream)),
+           "rg_pinv_track_noalloc")
+
+
+def pinv_track_noalloc_max_bytes():
+    return int(lib().rg_pinv_track_noalloc_max_bytes())
 
 
 def pinv_track(A, Y, r_max=None, eps=None, stream=None):
