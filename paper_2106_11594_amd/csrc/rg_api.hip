@@ -31,6 +31,7 @@ struct rg_ctx {
     uint32_t *d_counter = nullptr;  // one queue head per kernel family (RG_MAX_FAMILIES)
     void *d_state = nullptr;
     double *d_p = nullptr;
+    double *d_h = nullptr;       // H^-1 of the factored-form streams
     double *d_w = nullptr;
     double *d_big = nullptr;     // scratch of the multi-CU single-stream path (null if unused)
     std::vector<StreamMeta> h_meta;
@@ -55,10 +56,17 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
     std::vector<StreamMeta> meta;
-    size_t state_elems = 0, p_elems = 0, w_elems = 0, x_elems = 0;
+    size_t state_elems = 0, p_elems = 0, h_elems = 0, w_elems = 0, x_elems = 0;
 };
 
-Layout plan_layout(int32_t B, const int32_t *m, const int32_t *r_max, size_t esize) {
+// Kernel class of a stream (-1: generic kernel), and whether that class keeps
+// the dual basis in factored form (the blocked on-chip classes do).
+int stream_class(int m, int r_max, int dtype, uint32_t opts) {
+    const bool generic = (opts & (RG_OPT_GENERIC_KERNEL | RG_OPT_ORTHOGONAL | RG_OPT_ORTHONORMAL)) != 0;
+    return generic ? -1 : rg::choose_class(m, r_max, dtype);
+}
+
+Layout plan_layout(int32_t B, const int32_t *m, const int32_t *r_max, size_t esize, int dtype, uint32_t opts) {
     Layout L;
     L.meta.resize(B);
     const size_t quantum = 16 / esize;  // keep every block 16-byte aligned
@@ -69,7 +77,12 @@ Layout plan_layout(int32_t B, const int32_t *m, const int32_t *r_max, size_t esi
         M.ldm = (int32_t)align_up((size_t)M.m, quantum);
         M.r = 0;
         M.flags = 0;
-        M.cls = -1;
+        M.cls = stream_class(M.m, M.r_max, dtype, opts);
+        M.h_off = -1;
+        if (rg::class_factored(M.cls)) {
+            M.h_off = (int64_t)L.h_elems;
+            L.h_elems += align_up((size_t)M.r_max * M.r_max, 2);
+        }
         M.state_off = (int64_t)L.state_elems;
         L.state_elems += align_up(2 * (size_t)M.r_max * M.ldm, quantum);
         M.p_off = (int64_t)L.p_elems;
@@ -89,6 +102,7 @@ size_t ws_size(const Layout &L, int B, size_t esize, size_t big_doubles) {
     off += 256;  // counters
     off += align_up(L.state_elems * esize, 256);
     off += align_up(L.p_elems * sizeof(double), 256);
+    off += align_up(L.h_elems * sizeof(double), 256);
     off += align_up(L.w_elems * sizeof(double), 256);
     off += align_up(big_doubles * sizeof(double), 256);
     return off;
@@ -146,6 +160,7 @@ rg_status push_impl(rg_ctx *h, const void *gamma, const void *y, const int64_t *
     a.meta = h->d_meta;
     a.state = (T *)h->d_state;
     a.preg = h->d_p;
+    a.hreg = h->d_h;
     a.wreg = h->d_w;
     a.gamma = (const T *)gamma;
     a.y = (const T *)y;
@@ -290,7 +305,7 @@ size_t rg_workspace_bytes(int32_t B, const int32_t *m, const int32_t *r_max, int
     for (int b = 0; b < B; ++b)
         if (m[b] <= 0) return 0;
     const size_t es = dtype == RG_F64 ? 8 : 4;
-    Layout L = plan_layout(B, m, r_max, es);
+    Layout L = plan_layout(B, m, r_max, es, dtype, 0);
     const StreamMeta &M0 = L.meta[0];
     const bool big = B == 1 && M0.m >= rg::BIG_M_MIN && rg::choose_class(M0.m, M0.r_max, dtype) < 0;
     return ws_size(L, B, es, big ? rg::big_scratch_doubles(M0.m, M0.r_max) : 0);
@@ -323,14 +338,12 @@ static rg_status batch_init(rg_handle *out, int32_t B, const int32_t *m, const i
         delete h;
         return RG_E_DEVICE;
     }
-    Layout L = plan_layout(B, m, r_max, h->esize);
+    // kernel family per stream (the orthogonal factorization variants run in
+    // the generic kernel only)
+    Layout L = plan_layout(B, m, r_max, h->esize, h->dtype, o.flags);
     h->h_meta = L.meta;
-    // kernel family per stream
     for (int b = 0; b < B; ++b) {
         StreamMeta &M = h->h_meta[b];
-        // the orthogonal factorization variants run in the generic kernel only
-        const bool generic = (o.flags & (RG_OPT_GENERIC_KERNEL | RG_OPT_ORTHOGONAL | RG_OPT_ORTHONORMAL)) != 0;
-        M.cls = generic ? -1 : rg::choose_class(M.m, M.r_max, h->dtype);
         if (M.cls < 0) {
             h->m_max_generic = std::max(h->m_max_generic, M.m);
             h->rmax_max_generic = std::max(h->rmax_max_generic, M.r_max);
@@ -372,6 +385,8 @@ static rg_status batch_init(rg_handle *out, int32_t B, const int32_t *m, const i
     p += align_up(L.state_elems * h->esize, 256);
     h->d_p = (double *)p;
     p += align_up(L.p_elems * sizeof(double), 256);
+    h->d_h = (double *)p;
+    p += align_up(L.h_elems * sizeof(double), 256);
     h->d_w = (double *)p;
     p += align_up(L.w_elems * sizeof(double), 256);
     if (big) h->d_big = (double *)p;
@@ -448,10 +463,10 @@ rg_status rg_batch_push(rg_handle h, const void *gamma, const void *y, const int
 rg_status rg_batch_solution(rg_handle h, void *x) {
     if (!valid_handle(h) || !x) return RG_E_INVALID;
     hipError_t e = h->dtype == RG_F64
-                       ? rg::launch_solution<double>(h->d_meta, h->B, (const double *)h->d_state, h->d_w,
-                                                     (double *)x, h->stream)
-                       : rg::launch_solution<float>(h->d_meta, h->B, (const float *)h->d_state, h->d_w,
-                                                    (float *)x, h->stream);
+                       ? rg::launch_solution<double>(h->d_meta, h->B, (const double *)h->d_state, h->d_h, h->d_w,
+                                                     (double *)x, h->rmax_max_all, h->stream)
+                       : rg::launch_solution<float>(h->d_meta, h->B, (const float *)h->d_state, h->d_h, h->d_w,
+                                                    (float *)x, h->rmax_max_all, h->stream);
     return e == hipSuccess ? RG_OK : RG_E_DEVICE;
 }
 
@@ -558,7 +573,13 @@ rg_status rg_batch_get_state(rg_handle h, int32_t b, void *C, void *Ct, void *Pi
     const size_t pitch = (size_t)S.ldm * es;
     if (C) HIPCHK(hipMemcpy2DAsync(C, (size_t)S.m * es, base, pitch, (size_t)S.m * es, S.r, hipMemcpyDeviceToDevice,
                                    h->stream));
-    if (Ct)
+    if (Ct && S.h_off >= 0)  // factored form: Ct = H^-1 C formed on the fly
+        HIPCHK(h->dtype == RG_F64
+                   ? rg::launch_ctilde<double>(h->d_meta, b, (const double *)h->d_state, h->d_h, (double *)Ct, S.r,
+                                               h->stream)
+                   : rg::launch_ctilde<float>(h->d_meta, b, (const float *)h->d_state, h->d_h, (float *)Ct, S.r,
+                                              h->stream));
+    else if (Ct)
         HIPCHK(hipMemcpy2DAsync(Ct, (size_t)S.m * es, base + (size_t)S.r_max * pitch, pitch, (size_t)S.m * es, S.r,
                                 hipMemcpyDeviceToDevice, h->stream));
     if (Pinv)
@@ -575,10 +596,10 @@ rg_status rg_batch_adjoint(rg_handle h, const void *A, const void *Y, const int6
     if (!valid_handle(h) || !A || !Y || !row_ptr || !a_off || !g || !dA || !dY) return RG_E_INVALID;
     hipError_t e =
         h->dtype == RG_F64
-            ? rg::launch_adjoint<double>(h->d_meta, h->B, (const double *)h->d_state, h->d_p, h->d_w,
+            ? rg::launch_adjoint<double>(h->d_meta, h->B, (const double *)h->d_state, h->d_p, h->d_h, h->d_w,
                                          (const double *)A, (const double *)Y, row_ptr, a_off, (const double *)g,
                                          (double *)dA, (double *)dY, h->m_max_all, h->rmax_max_all, h->stream)
-            : rg::launch_adjoint<float>(h->d_meta, h->B, (const float *)h->d_state, h->d_p, h->d_w,
+            : rg::launch_adjoint<float>(h->d_meta, h->B, (const float *)h->d_state, h->d_p, h->d_h, h->d_w,
                                         (const float *)A, (const float *)Y, row_ptr, a_off, (const float *)g,
                                         (float *)dA, (float *)dY, h->m_max_all, h->rmax_max_all, h->stream);
     return e == hipSuccess ? RG_OK : RG_E_DEVICE;
@@ -588,9 +609,9 @@ rg_status rg_batch_pinv(rg_handle h, const void *A, const int64_t *row_ptr, cons
     if (!valid_handle(h) || !A || !row_ptr || !a_off || !Ap) return RG_E_INVALID;
     hipError_t e =
         h->dtype == RG_F64
-            ? rg::launch_pinv<double>(h->d_meta, h->B, (const double *)h->d_state, h->d_p, (const double *)A, row_ptr,
+            ? rg::launch_pinv<double>(h->d_meta, h->B, (const double *)h->d_state, h->d_p, h->d_h, (const double *)A, row_ptr,
                                       a_off, (double *)Ap, h->m_max_all, h->rmax_max_all, h->stream)
-            : rg::launch_pinv<float>(h->d_meta, h->B, (const float *)h->d_state, h->d_p, (const float *)A, row_ptr,
+            : rg::launch_pinv<float>(h->d_meta, h->B, (const float *)h->d_state, h->d_p, h->d_h, (const float *)A, row_ptr,
                                      a_off, (float *)Ap, h->m_max_all, h->rmax_max_all, h->stream);
     return e == hipSuccess ? RG_OK : RG_E_DEVICE;
 }

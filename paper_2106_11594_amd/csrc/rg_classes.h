@@ -11,6 +11,9 @@ namespace rg {
 // stream goes to the generic kernel (FP64 state, or too large for the chip).
 int choose_class(int m, int r_max, int dtype);
 int class_rmax(int cls);
+// Whether class cls keeps the dual basis in factored form (Ct = H^-1 C, with
+// H^-1 = (C C^T)^-1 in FP64): the blocked kernel's variants do.
+bool class_factored(int cls);
 // Raise the dynamic-LDS limit of class cls's kernel to what rows_alloc needs
 // (once per handle, at init).
 hipError_t prepare_class(int cls, int rows_alloc);

@@ -291,16 +291,53 @@ __global__ void k_reset_streams(StreamMeta *meta, int B) {
     }
 }
 
-// x_b = Ct_b^T w_b, FP64 sums, one workgroup per stream.
+// dst[k] = sum_l H[k][l] v[l] for k < r (H symmetric r_max x r_max, row-major;
+// thread k reads column k, so the reads of a wave coalesce).
+__device__ inline void hmul(const double *H, int rmax, const double *v, double *dst, int r) {
+    for (int k = threadIdx.x; k < r; k += NT) {
+        double acc = 0.0;
+        for (int l = 0; l < r; ++l) acc += H[(size_t)l * rmax + k] * v[l];
+        dst[k] = acc;
+    }
+}
+
+// x_b = Ct_b^T w_b, FP64 sums, one workgroup per stream.  Factored-form
+// streams (Ct = H^-1 C) first form u = H^-1 w, then x = C^T u.
 template <typename T>
-__global__ void __launch_bounds__(NT) k_solution(const StreamMeta *meta, const T *state, const double *wreg, T *x) {
+__global__ void __launch_bounds__(NT) k_solution(const StreamMeta *meta, const T *state, const double *hreg,
+                                                 const double *wreg, T *x) {
+    extern __shared__ double su[];
     const StreamMeta M = meta[blockIdx.x];
-    const T *Ct = state + M.state_off + (size_t)M.r_max * M.ldm;
     const double *w = wreg + M.w_off;
+    const T *B;
+    if (M.h_off >= 0) {
+        hmul(hreg + M.h_off, M.r_max, w, su, M.r);
+        __syncthreads();
+        w = su;
+        B = state + M.state_off;
+    } else {
+        B = state + M.state_off + (size_t)M.r_max * M.ldm;
+    }
     for (int j = threadIdx.x; j < M.m; j += NT) {
         double acc = 0.0;
-        for (int k = 0; k < M.r; ++k) acc += (double)Ct[(size_t)k * M.ldm + j] * w[k];
+        for (int k = 0; k < M.r; ++k) acc += (double)B[(size_t)k * M.ldm + j] * w[k];
         x[M.x_off + j] = (T)acc;
+    }
+}
+
+// Ct = H^-1 C of one factored-form stream, FP64 sums, rounded to T: thread
+// (k, j-range) forms row k of Ct.
+template <typename T>
+__global__ void __launch_bounds__(NT) k_ctilde(const StreamMeta *meta, int b, const T *state, const double *hreg,
+                                               T *dst, int r) {
+    const StreamMeta M = meta[b];
+    const T *C = state + M.state_off;
+    const double *H = hreg + M.h_off;
+    for (int64_t idx = blockIdx.x * (int64_t)NT + threadIdx.x; idx < (int64_t)r * M.m; idx += (int64_t)gridDim.x * NT) {
+        const int k = (int)(idx / M.m), j = (int)(idx - (int64_t)k * M.m);
+        double acc = 0.0;
+        for (int l = 0; l < r; ++l) acc += H[(size_t)k * M.r_max + l] * (double)C[(size_t)l * M.ldm + j];
+        dst[idx] = (T)acc;
     }
 }
 
@@ -308,32 +345,47 @@ __global__ void __launch_bounds__(NT) k_solution(const StreamMeta *meta, const T
 //   x = Ct^T w, u = Ct g, v = Ct x, s = Ct^T P^-1 u, t = Ct^T P^-1 v, p = g - C^T u;
 // then one pass over the rows of A: a_i = A_i s, b_i = A_i t, rho_i = Y_i - A_i x,
 //   dY_i = a_i, dA_i = -a_i x + rho_i s + b_i p.
+// Factored-form streams (Ct = H^-1 C) apply Ct and Ct^T as H^-1 C and
+// C^T H^-1, with the same algebra.
 template <typename T>
 __global__ void __launch_bounds__(NT) k_adjoint(const StreamMeta *meta, const T *state, const double *preg,
-                                                const double *wreg, const T *A, const T *Y, const int64_t *row_ptr,
-                                                const int64_t *a_off, const T *g, T *dA, T *dY, int m_max,
-                                                int r_max_max) {
+                                                const double *hreg, const double *wreg, const T *A, const T *Y,
+                                                const int64_t *row_ptr, const int64_t *a_off, const T *g, T *dA,
+                                                T *dY, int m_max, int r_max_max) {
     extern __shared__ double smem[];
     const int b = blockIdx.x;
     const StreamMeta M = meta[b];
     const int m = M.m, r = M.r, ldm = M.ldm, rmax = M.r_max;
+    const bool fd = M.h_off >= 0;
     const T *C = state + M.state_off;
-    const T *Ct = C + (size_t)rmax * ldm;
+    const T *Ct = fd ? C : C + (size_t)rmax * ldm;  // factored form: the rows multiplied by H^-1
+    const double *H = fd ? hreg + M.h_off : nullptr;
     const double *P = preg + M.p_off;
     const double *w = wreg + M.w_off;
     double *sx = smem, *sg = sx + m_max, *ss = sg + m_max, *st = ss + m_max, *sp = st + m_max;
     double *su = sp + m_max, *sv = su + r_max_max, *su2 = sv + r_max_max, *sv2 = su2 + r_max_max;
+    double *sh = sv2 + r_max_max, *sh2 = sh + r_max_max;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    if (fd) {
+        hmul(H, rmax, w, sh, r);  // x = C^T (H^-1 w)
+        __syncthreads();
+    }
+    const double *wx = fd ? sh : w;
     for (int j = tid; j < m; j += NT) {
         double acc = 0.0;
-        for (int k = 0; k < r; ++k) acc += (double)Ct[(size_t)k * ldm + j] * w[k];
+        for (int k = 0; k < r; ++k) acc += (double)Ct[(size_t)k * ldm + j] * wx[k];
         sx[j] = acc;
         sg[j] = (double)g[M.x_off + j];
     }
     __syncthreads();
-    project<T, double>(Ct, ldm, sg, su, r, m);
-    project<T, double>(Ct, ldm, sx, sv, r, m);
+    project<T, double>(Ct, ldm, sg, fd ? sh : su, r, m);
+    project<T, double>(Ct, ldm, sx, fd ? sh2 : sv, r, m);
     __syncthreads();
+    if (fd) {
+        hmul(H, rmax, sh, su, r);
+        hmul(H, rmax, sh2, sv, r);
+        __syncthreads();
+    }
     for (int i = tid; i < r; i += NT) {
         double a1 = 0.0, a2 = 0.0;
         for (int k = 0; k < r; ++k) {
@@ -345,6 +397,13 @@ __global__ void __launch_bounds__(NT) k_adjoint(const StreamMeta *meta, const T 
         sv2[i] = a2;
     }
     __syncthreads();
+    if (fd) {
+        hmul(H, rmax, su2, sh, r);
+        hmul(H, rmax, sv2, sh2, r);
+        __syncthreads();
+        su2 = sh;
+        sv2 = sh2;
+    }
     for (int j = tid; j < m; j += NT) {
         double a1 = 0.0, a2 = 0.0, a3 = sg[j];
         for (int k = 0; k < r; ++k) {
@@ -395,16 +454,18 @@ __global__ void __launch_bounds__(NT) k_adjoint(const StreamMeta *meta, const T 
 // A^+ = Ct^T P^-1 B^T with B = A Ct^T), one row of A at a time: column i of
 // A^+ is Ct^T P^-1 (Ct A_i^T).  FP64 sums; A^+ is m x n row-major.
 template <typename T>
-__global__ void __launch_bounds__(NT) k_pinv(const StreamMeta *meta, const T *state, const double *preg, const T *A,
-                                             const int64_t *row_ptr, const int64_t *a_off, T *Ap, int m_max,
-                                             int r_max_max) {
+__global__ void __launch_bounds__(NT) k_pinv(const StreamMeta *meta, const T *state, const double *preg,
+                                             const double *hreg, const T *A, const int64_t *row_ptr,
+                                             const int64_t *a_off, T *Ap, int m_max, int r_max_max) {
     extern __shared__ double smem[];
     const int b = blockIdx.x;
     const StreamMeta M = meta[b];
     const int m = M.m, r = M.r, ldm = M.ldm, rmax = M.r_max;
-    const T *Ct = state + M.state_off + (size_t)rmax * ldm;
+    const bool fd = M.h_off >= 0;  // factored form: Ct = H^-1 C
+    const T *Ct = state + M.state_off + (fd ? 0 : (size_t)rmax * ldm);
+    const double *H = fd ? hreg + M.h_off : nullptr;
     const double *P = preg + M.p_off;
-    double *sa = smem, *sb = sa + m_max, *sq = sb + r_max_max;
+    double *sa = smem, *sb = sa + m_max, *sq = sb + r_max_max, *st = sq + r_max_max;
     const int64_t i0 = row_ptr[b], i1 = row_ptr[b + 1], n = i1 - i0;
     const T *Ab = A + a_off[b];
     T *Apb = Ap + a_off[b];
@@ -412,17 +473,27 @@ __global__ void __launch_bounds__(NT) k_pinv(const StreamMeta *meta, const T *st
     for (int64_t i = 0; i < n; ++i) {
         for (int j = tid; j < m; j += NT) sa[j] = (double)Ab[i * m + j];
         __syncthreads();
-        project<T, double>(Ct, ldm, sa, sb, r, m);  // b = Ct A_i^T
+        project<T, double>(Ct, ldm, sa, fd ? st : sb, r, m);  // b = Ct A_i^T
         __syncthreads();
+        if (fd) {
+            hmul(H, rmax, st, sb, r);
+            __syncthreads();
+        }
         for (int a2 = tid; a2 < r; a2 += NT) {       // q = P^-1 b (symmetric: column reads coalesce)
             double acc = 0.0;
             for (int k = 0; k < r; ++k) acc += P[(size_t)k * rmax + a2] * sb[k];
             sq[a2] = acc;
         }
         __syncthreads();
+        const double *q = sq;
+        if (fd) {
+            hmul(H, rmax, sq, st, r);
+            __syncthreads();
+            q = st;
+        }
         for (int j = tid; j < m; j += NT) {
             double acc = 0.0;
-            for (int k = 0; k < r; ++k) acc += (double)Ct[(size_t)k * ldm + j] * sq[k];
+            for (int k = 0; k < r; ++k) acc += (double)Ct[(size_t)k * ldm + j] * q[k];
             Apb[(int64_t)j * n + i] = (T)acc;
         }
         __syncthreads();
@@ -432,18 +503,33 @@ __global__ void __launch_bounds__(NT) k_pinv(const StreamMeta *meta, const T *st
 }  // namespace
 
 template <typename T>
-hipError_t launch_pinv(const StreamMeta *meta, int B, const T *state, const double *preg, const T *A,
-                       const int64_t *row_ptr, const int64_t *a_off, T *Ap, int m_max, int r_max_max, hipStream_t s) {
-    const size_t lds = sizeof(double) * ((size_t)m_max + 2 * (size_t)r_max_max);
+hipError_t launch_pinv(const StreamMeta *meta, int B, const T *state, const double *preg, const double *hreg,
+                       const T *A, const int64_t *row_ptr, const int64_t *a_off, T *Ap, int m_max, int r_max_max,
+                       hipStream_t s) {
+    const size_t lds = sizeof(double) * ((size_t)m_max + 3 * (size_t)r_max_max);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_pinv<T>, dim3(B), dim3(NT), lds, s, meta, state, preg, A, row_ptr, a_off, Ap, m_max,
+    hipLaunchKernelGGL(k_pinv<T>, dim3(B), dim3(NT), lds, s, meta, state, preg, hreg, A, row_ptr, a_off, Ap, m_max,
                        r_max_max);
     return hipGetLastError();
 }
-template hipError_t launch_pinv<float>(const StreamMeta *, int, const float *, const double *, const float *,
-                                       const int64_t *, const int64_t *, float *, int, int, hipStream_t);
+template hipError_t launch_pinv<float>(const StreamMeta *, int, const float *, const double *, const double *,
+                                       const float *, const int64_t *, const int64_t *, float *, int, int,
+                                       hipStream_t);
 template hipError_t launch_pinv<double>(const StreamMeta *, int, const double *, const double *, const double *,
-                                        const int64_t *, const int64_t *, double *, int, int, hipStream_t);
+                                        const double *, const int64_t *, const int64_t *, double *, int, int,
+                                        hipStream_t);
+
+template <typename T>
+hipError_t launch_ctilde(const StreamMeta *meta, int b, const T *state, const double *hreg, T *dst, int r,
+                         hipStream_t s) {
+    if (r <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ctilde<T>, dim3(64), dim3(NT), 0, s, meta, b, state, hreg, dst, r);
+    return hipGetLastError();
+}
+template hipError_t launch_ctilde<float>(const StreamMeta *, int, const float *, const double *, float *, int,
+                                         hipStream_t);
+template hipError_t launch_ctilde<double>(const StreamMeta *, int, const double *, const double *, double *, int,
+                                          hipStream_t);
 
 template <typename T>
 hipError_t launch_push_generic(const PushArgs<T> &a, int grid, int m_max, int r_max_max, hipStream_t s) {
@@ -465,35 +551,37 @@ hipError_t launch_reset_streams(StreamMeta *meta, int B, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t launch_solution(const StreamMeta *meta, int B, const T *state, const double *wreg, T *x,
-                           hipStream_t s) {
-    hipLaunchKernelGGL(k_solution<T>, dim3(B), dim3(NT), 0, s, meta, state, wreg, x);
+hipError_t launch_solution(const StreamMeta *meta, int B, const T *state, const double *hreg, const double *wreg,
+                           T *x, int r_max_max, hipStream_t s) {
+    const size_t lds = sizeof(double) * (size_t)r_max_max;
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_solution<T>, dim3(B), dim3(NT), lds, s, meta, state, hreg, wreg, x);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_adjoint(const StreamMeta *meta, int B, const T *state, const double *preg, const double *wreg,
-                          const T *A, const T *Y, const int64_t *row_ptr, const int64_t *a_off, const T *g, T *dA,
-                          T *dY, int m_max, int r_max_max, hipStream_t s) {
-    const size_t lds = sizeof(double) * (5 * (size_t)m_max + 4 * (size_t)r_max_max);
+hipError_t launch_adjoint(const StreamMeta *meta, int B, const T *state, const double *preg, const double *hreg,
+                          const double *wreg, const T *A, const T *Y, const int64_t *row_ptr, const int64_t *a_off,
+                          const T *g, T *dA, T *dY, int m_max, int r_max_max, hipStream_t s) {
+    const size_t lds = sizeof(double) * (5 * (size_t)m_max + 6 * (size_t)r_max_max);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_adjoint<T>, dim3(B), dim3(NT), lds, s, meta, state, preg, wreg, A, Y, row_ptr, a_off, g,
-                       dA, dY, m_max, r_max_max);
+    hipLaunchKernelGGL(k_adjoint<T>, dim3(B), dim3(NT), lds, s, meta, state, preg, hreg, wreg, A, Y, row_ptr, a_off,
+                       g, dA, dY, m_max, r_max_max);
     return hipGetLastError();
 }
 
 template hipError_t launch_push_generic<float>(const PushArgs<float> &, int, int, int, hipStream_t);
 template hipError_t launch_push_generic<double>(const PushArgs<double> &, int, int, int, hipStream_t);
-template hipError_t launch_solution<float>(const StreamMeta *, int, const float *, const double *, float *,
-                                           hipStream_t);
-template hipError_t launch_solution<double>(const StreamMeta *, int, const double *, const double *, double *,
-                                            hipStream_t);
+template hipError_t launch_solution<float>(const StreamMeta *, int, const float *, const double *, const double *,
+                                           float *, int, hipStream_t);
+template hipError_t launch_solution<double>(const StreamMeta *, int, const double *, const double *,
+                                            const double *, double *, int, hipStream_t);
 template hipError_t launch_adjoint<float>(const StreamMeta *, int, const float *, const double *, const double *,
-                                          const float *, const float *, const int64_t *, const int64_t *,
-                                          const float *, float *, float *, int, int, hipStream_t);
+                                          const double *, const float *, const float *, const int64_t *,
+                                          const int64_t *, const float *, float *, float *, int, int, hipStream_t);
 template hipError_t launch_adjoint<double>(const StreamMeta *, int, const double *, const double *,
-                                           const double *, const double *, const double *, const int64_t *,
-                                           const int64_t *, const double *, double *, double *, int, int,
-                                           hipStream_t);
+                                           const double *, const double *, const double *, const double *,
+                                           const int64_t *, const int64_t *, const double *, double *, double *, int,
+                                           int, hipStream_t);
 
 }  // namespace rg

@@ -18,6 +18,9 @@ struct StreamMeta {
     int64_t w_off;      // offset of w (doubles) in the w region
     int64_t x_off;      // offset of x in packed solution vectors
     int64_t rows_seen;  // rows applied since the last reset
+    int64_t h_off;      // offset of H^-1 = (C C^T)^-1 (doubles, r_max x r_max) in the H region, or -1:
+                        // streams with H^-1 keep the dual basis in factored form, Ct = H^-1 C, and
+                        // their Ct rows in the state are not maintained
 };
 
 constexpr uint32_t FLAG_NONFINITE = 0x1u;
@@ -38,6 +41,7 @@ struct PushArgs {
     uint32_t *counter;       // work-queue head, zeroed before the launch
     T *state;
     double *preg;            // P^-1 blocks (FP64 for both state types)
+    double *hreg;            // H^-1 blocks of factored-form streams (FP64)
     double *wreg;
     const T *gamma;
     const T *y;
@@ -60,14 +64,19 @@ size_t big_scratch_doubles(int m, int rmax);
 template <typename T>
 hipError_t launch_push_big(const PushArgs<T> &a, double *scratch, int m, int rmax, int num_cus, hipStream_t s);
 template <typename T>
-hipError_t launch_pinv(const StreamMeta *meta, int B, const T *state, const double *preg, const T *A,
-                       const int64_t *row_ptr, const int64_t *a_off, T *Ap, int m_max, int r_max_max, hipStream_t s);
+hipError_t launch_pinv(const StreamMeta *meta, int B, const T *state, const double *preg, const double *hreg,
+                       const T *A, const int64_t *row_ptr, const int64_t *a_off, T *Ap, int m_max, int r_max_max,
+                       hipStream_t s);
 template <typename T>
-hipError_t launch_solution(const StreamMeta *meta, int B, const T *state, const double *wreg, T *x,
-                           hipStream_t s);
+hipError_t launch_solution(const StreamMeta *meta, int B, const T *state, const double *hreg, const double *wreg,
+                           T *x, int r_max_max, hipStream_t s);
 template <typename T>
-hipError_t launch_adjoint(const StreamMeta *meta, int B, const T *state, const double *preg, const double *wreg,
-                          const T *A, const T *Y, const int64_t *row_ptr, const int64_t *a_off, const T *g, T *dA,
-                          T *dY, int m_max, int r_max_max, hipStream_t s);
+hipError_t launch_adjoint(const StreamMeta *meta, int B, const T *state, const double *preg, const double *hreg,
+                          const double *wreg, const T *A, const T *Y, const int64_t *row_ptr, const int64_t *a_off,
+                          const T *g, T *dA, T *dY, int m_max, int r_max_max, hipStream_t s);
+// Ct = H^-1 C of stream b (factored-form streams), r x m row-major into dst.
+template <typename T>
+hipError_t launch_ctilde(const StreamMeta *meta, int b, const T *state, const double *hreg, T *dst, int r,
+                         hipStream_t s);
 
 }  // namespace rg

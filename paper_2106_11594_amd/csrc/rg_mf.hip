@@ -1,43 +1,59 @@
-// Batched rank-Greville update with FP32 state on chip and blocks of dependent
+// Batched rank-Greville update with the stream state on chip and blocks of
 // rows applied through FP64 matrix-core products (v_mfma_f64_16x16x4f64).
+//
+// The dual basis Ct = (C C^T)^-1 C of Section 2.1 is kept in factored form:
+// C (the accepted raw rows, exact in FP32 for FP32 inputs) and
+// H^-1 = (C C^T)^-1 in FP64, so that every projection gamma = Ct Gamma is
+// formed as H^-1 (C Gamma) with FP64 arithmetic on exact FP32 rows.  An
+// FP32-stored Ct would perturb the projections by about 2^-24 kappa(C), and
+// that error does not cancel in x; in factored form it is about
+// 2^-52 kappa(C)^2.  The independent update of Theorem 6 (Ct <- [Ct - gamma
+// K^T; K^T]) is, on the factors, the bordering of H^-1 with the rejection's
+// squared norm as Schur complement:
+//   H^-1 <- [[H^-1 + gamma gamma^T / s, -gamma / s], [-gamma^T / s, 1 / s]],
+//   s = ||Gamma_r||^2,
+// O(r^2) instead of the O(r m) update of an explicit Ct.
 //
 // One workgroup of NW waves (4 or 8) owns one stream for a whole push.  Lane
 // l of wave w has i = l & 15 and g = l >> 4.  Residency:
-//   Ct    LDS, FP32, row-major, leading dimension MMAX.  Logical float4 chunk
+//   C     LDS, FP32, row-major, leading dimension MMAX.  Logical float4 chunk
 //         c of row k sits at physical chunk c ^ (k & 15), so that the 16 rows
 //         a matrix-core operand touches fall into different banks;
-//   C     registers, FP32: c[s][tau] = C[4s + g][16 (w + NW tau) + i]
-//         (the A operand of C^T for column tile w + NW tau, K-step s); for
-//         RMAX = 128, where C and P^-1 would not both fit, C is read in the
-//         same pattern from the stream's state in global memory (L2);
-//   P^-1  registers, FP64, 16 x 16 output tiles (u', u) for the column tiles
-//         u = w + NW ups of this wave: p[u'][ups][v] = P^-1[16u' + 4v + g][16u + i];
+//   P^-1, H^-1  registers, FP64, 16 x 16 output tiles (u', u) for the column
+//         tiles u = w + NW ups of this wave:
+//         p[u'][ups][v] = P^-1[16u' + 4v + g][16u + i], h likewise;
 //   w     registers, FP64: wr[ups][v] = w[16 (w + NW ups) + 4v + g].
 // The matrix-core operands of v_mfma_f64_16x16x4f64 are A[i][g] and B[g][i]
 // on lane (i, g), and the result D[4v + g][i] sits in register v of lane
 // (i, g); the layouts above are chosen so that results feed later products
-// without shuffles.
+// without shuffles.  P^-1 and H^-1 are symmetric, so the same registers are
+// the A operand of products with them.
 //
 // Rows are taken in two modes.
-//  Row mode (Algorithm 1, one row): gamma = Ct Gamma over LDS with 16-lane
-//   DPP sums; C^T gamma, zeta = P^-1 gamma and gamma^T w per column tile with
-//   the register-resident C and P^-1 and one reduce-scatter over the 4 lane
-//   groups; rank test on workgroup sums; then the dependent update of P^-1
-//   and w (Theorems 5 and 6), or the independent one (second projection pass,
-//   Ct <- [Ct - gamma K^T; K^T], appends to C, P^-1 and w; Theorems 4 and 6).
-//  Block mode (up to 16 rows): G = Gamma_blk Ct^T and the rejections
-//   R = Gamma_blk - G C on the matrix cores; the rank test of Section 3 on
-//   every row; the longest prefix of dependent rows is applied at once.
-//   Applying the dependent rows j = 0..nd-1 one after another is the same as
-//   the Woodbury form with Z = P^-1 G^T, S = I + G Z:
+//  Row mode (Algorithm 1, one row): v = C Gamma over LDS with 16-lane DPP
+//   sums; gamma = H^-1 v, C^T gamma, zeta = P^-1 gamma and gamma^T w per
+//   column tile with one reduce-scatter over the 4 lane groups each; rank
+//   test on workgroup sums; then the dependent update of P^-1 and w
+//   (Theorems 5 and 6), or the independent one (bordering of H^-1 and P^-1,
+//   appends to C and w; Theorems 4 and 6).
+//  Block mode (up to 16 rows): V = Gamma_blk C^T, G = V H^-1 and the
+//   rejections R = Gamma_blk - G C on the matrix cores; the rank test of
+//   Section 3 on every row.
+//   A prefix of dependent rows (nd rows) is applied at once: applying the
+//   rows j = 0..nd-1 one after another is the same as the Woodbury form with
+//   Z = P^-1 G^T, S = I + G Z:
 //     P^-1 <- P^-1 - Z S^-1 Z^T,   w <- w + Z S^-1 (y - G w),
 //   and the pivots of the Cholesky factor S = L L^T are exactly the
 //   sequential Greville denominators 1 + gamma_j^T P_j^-1 gamma_j, so their
 //   test is the same.  With T = Z L^-T the updates are P^-1 -= T T^T and
-//   w += T (L^-1 (y - G w)).  The first row that is not dependent is then taken
-//   in row mode.
-// The kernel enters block mode after a dependent row and leaves it at an
-// independent one; every branch is on workgroup-uniform values.
+//   w += T (L^-1 (y - G w)).
+//   A prefix of independent rows (ni rows) is appended at once: with
+//   R R^T = L L^T (its pivots are the sequential squared rejection norms, so
+//   the rank test of every row is the row-by-row test) and W = L^-1,
+//     H^-1 <- [[H^-1, 0], [0, 0]] + U U^T,  U = [G^T W^T; -W^T],
+//   C <- [C; Gamma_blk], P^-1 <- diag(P^-1, I), w <- [w; y_blk].
+//   The first row of the other kind ends the block.
+// Every branch is on workgroup-uniform values.
 #include "rg_classes.h"
 #include "rg_lanes.h"
 
@@ -62,20 +78,9 @@ __device__ inline double rsqrt_f64(double x) {
     return y;
 }
 
-// FP64 value of a register-resident FP32 state element.  The empty asm keeps
-// the compiler from hoisting the conversion out of the row loop, which would
-// keep an FP64 copy of all of C live and double its register footprint.
-__device__ inline double f64_of(float v) {
-    asm volatile("" : "+v"(v));
-    return (double)v;
-}
-
-template <int RMAX_, int MMAX_, int NW_, bool CG_>
+template <int RMAX_, int MMAX_, int NW_>
 struct MF {
     static constexpr int RMAX = RMAX_, MMAX = MMAX_, NW = NW_;
-    // CG: C is read from the stream's state in global memory (L2-resident)
-    // instead of registers; used where C and P^-1 together would not fit.
-    static constexpr bool CG = CG_;
     static_assert((RMAX == 64 || RMAX == 128) && (RMAX / 16) % NW == 0, "whole row tiles per wave");
     static_assert(MMAX % 64 == 0 && MMAX <= 256 && (NW == 4 || NW == 8), "4 or 8 waves");
     static constexpr int NT = 64 * NW;
@@ -83,7 +88,7 @@ struct MF {
     static constexpr int NTT = MMAX / 16, TPW = (NTT + NW - 1) / NW;  // 16-column tiles, per wave
     static_assert(TPW <= 4 && UPW <= 2, "one reduce-scatter holds the column and zeta totals");
     static constexpr int RS = 4 * NW;                                 // row stride of a thread in row mode
-    static constexpr int NB = RMAX / RS;                              // Ct rows per thread in row mode
+    static constexpr int NB = RMAX / RS;                              // C rows per thread in row mode
     static constexpr int KB = 16;                                     // rows per block
     static constexpr int CH = MMAX / 4;                               // float4 chunks per row
     // X1 (doubles): block-mode scalars and partial sums, or the row-mode vectors
@@ -95,16 +100,23 @@ struct MF {
     // variants whose LDS footprint lets two workgroups share a CU (m <= 192),
     // which then factor column by column (a panel's registers would not fit)
     static constexpr int OCC = (NW == 4 && MMAX <= 192) ? 2 : 1;
+    // HG: H^-1 stays in the stream's state in global memory (L2-resident) instead of
+    // registers, where P^-1 and H^-1 together would not fit (RMAX = 128).  It is
+    // only read by dependent rows, and each lane reads and writes its own tile
+    // elements, in the register layout, when rows are appended.
+    static constexpr bool HG = RMAX == 128;
     static constexpr int CBW = (NW == 4 && OCC == 1) ? 4 : 1;         // Cholesky panel width (1: column by column)
     static constexpr int X1_DW = X1_COL + 96;
-    static constexpr int X1_M = X1_SP;  // independent block: M, after the records are read
-    static constexpr int X1_GAM = 0, X1_ZETA = RMAX, X1_RED = 2 * RMAX, X1_GR = 2 * RMAX + 4 * NW;
+    static constexpr int X1_W = X1_SP;  // independent block: W = L^-1 (row-major 16 x 16), after the records are read
+    // row mode: gamma, zeta, v = C Gamma, the reduction records, Gamma_r (three separate
+    // vectors, so that no row writes one that a wave may still read for the row before)
+    static constexpr int X1_GAM = 0, X1_ZETA = RMAX, X1_V = 2 * RMAX, X1_RED = 3 * RMAX, X1_GR = 3 * RMAX + 4 * NW;
     static constexpr int X1_D = cmax(cmax(KB * MMAX / 2, X1_DW + RMAX), X1_GR + MMAX);
-    // X2 (doubles): G (16 x RMAX), then Z and T (RMAX x 16); or the row ring
+    // X2 (doubles): V and G (16 x RMAX), then Z, T or U (RMAX x 16); or the row ring
     static constexpr int X2_D = cmax(KB * RMAX, 3 * MMAX / 2);
 };
 
-// Swizzled positions of G[j][kk] (16 x RMAX) and of Z, T [kk][j] (RMAX x 16).
+// Swizzled positions of G[j][kk] (16 x RMAX) and of Z, T, U [kk][j] (RMAX x 16).
 template <int RMAX>
 __device__ inline int gpos(int j, int kk) { return j * RMAX + (kk ^ (4 * (j & 7))); }
 __device__ inline int zpos(int kk, int j) { return kk * 16 + (j ^ (4 * ((kk >> 1) & 3))); }
@@ -139,10 +151,10 @@ __global__ void __launch_bounds__(K::NT, K::OCC) k_push_mf(PushArgs<float> a, in
     constexpr int RMAX = K::RMAX, MMAX = K::MMAX, NU = K::NU, UPW = K::UPW, TPW = K::TPW;
     constexpr int NB = K::NB, KB = K::KB, CH = K::CH, NW = K::NW, NTT = K::NTT, RS = K::RS;
     extern __shared__ double smem[];
-    float *sct = reinterpret_cast<float *>(smem);  // ra x MMAX (ra: multiple of 16)
+    float *sct = reinterpret_cast<float *>(smem);  // C: ra x MMAX (ra: multiple of 16)
     double *x1 = smem + (size_t)ra * MMAX / 2;
     double *x2 = x1 + K::X1_D;
-    float *x1f = reinterpret_cast<float *>(x1);   // block rows, 16 x MMAX, swizzled like Ct
+    float *x1f = reinterpret_cast<float *>(x1);   // block rows, 16 x MMAX, swizzled like C
     float *ring = reinterpret_cast<float *>(x2);  // row mode: 3 rows of MMAX
 
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
@@ -152,8 +164,8 @@ __global__ void __launch_bounds__(K::NT, K::OCC) k_push_mf(PushArgs<float> a, in
     int r = M->r;
     uint32_t flags = M->flags;
     float *Cg = a.state + M->state_off;
-    float *Ctg = Cg + (size_t)rmax * ldm;
     double *Pg = a.preg + M->p_off;
+    double *Hg = a.hreg + M->h_off;
     double *wg = a.wreg + M->w_off;
     int64_t i0, i1, goff;
     if (a.row_ptr) {
@@ -177,24 +189,42 @@ __global__ void __launch_bounds__(K::NT, K::OCC) k_push_mf(PushArgs<float> a, in
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int j = 4 * c + e;
-            v[e] = (k < r && j < m) ? Ctg[(size_t)k * ldm + j] : 0.0f;
+            v[e] = (k < r && j < m) ? Cg[(size_t)k * ldm + j] : 0.0f;
         }
         *reinterpret_cast<float4 *>(sct + (size_t)k * MMAX + 4 * (c ^ (k & 15))) = make_float4(v[0], v[1], v[2], v[3]);
     }
     const int li = lane & 15, lg = lane >> 4;
-    constexpr int NCS = K::CG ? 1 : 4 * NU, NCT = K::CG ? 1 : TPW;
-    float c[NCS][NCT];
-    if constexpr (!K::CG) {
-#pragma unroll
-        for (int s = 0; s < 4 * NU; ++s)
-#pragma unroll
-            for (int tau = 0; tau < TPW; ++tau) {
-                const int row = 4 * s + lg, col = 16 * (wv + NW * tau) + li;
-                c[s][tau] = (row < r && col < m) ? Cg[(size_t)row * ldm + col] : 0.0f;
-            }
-    }
-    d4 p[NU][UPW];
+    constexpr int NUH = K::HG ? 1 : NU, UPWH = K::HG ? 1 : UPW;
+    d4 p[NU][UPW], h[NUH][UPWH];
     double wr[UPW][4];
+    // Tile (u2, u = wv + NW ups) of H^-1 for the current rank rr (entries past
+    // rr read as zero), and its store (entries past rr are not written)
+    auto hload = [&](int u2, int ups, int rr) -> d4 {
+        if constexpr (K::HG) {
+            const int col = 16 * (wv + NW * ups) + (lane & 15);
+            d4 o;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = 16 * u2 + 4 * v + (lane >> 4);
+                o[v] = (row < rr && col < rr) ? Hg[(size_t)row * rmax + col] : 0.0;
+            }
+            return o;
+        } else {
+            return h[u2][ups];
+        }
+    };
+    auto hstore = [&](int u2, int ups, const d4 &val, int rr) {
+        if constexpr (K::HG) {
+            const int col = 16 * (wv + NW * ups) + (lane & 15);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = 16 * u2 + 4 * v + (lane >> 4);
+                if (row < rr && col < rr) Hg[(size_t)row * rmax + col] = val[v];
+            }
+        } else {
+            h[u2][ups] = val;
+        }
+    };
 #pragma unroll
     for (int ups = 0; ups < UPW; ++ups) {
         const int col = 16 * (wv + NW * ups) + li;
@@ -203,7 +233,9 @@ __global__ void __launch_bounds__(K::NT, K::OCC) k_push_mf(PushArgs<float> a, in
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int row = 16 * u2 + 4 * v + lg;
-                p[u2][ups][v] = (row < r && col < r) ? Pg[(size_t)row * rmax + col] : 0.0;
+                const bool in = row < r && col < r;
+                p[u2][ups][v] = in ? Pg[(size_t)row * rmax + col] : 0.0;
+                if constexpr (!K::HG) h[u2][ups][v] = in ? Hg[(size_t)row * rmax + col] : 0.0;
             }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -236,7 +268,6 @@ __global__ void __launch_bounds__(K::NT, K::OCC) k_push_mf(PushArgs<float> a, in
         }
         ydst = (tid & 15) < nrows ? ysrc[tid & 15] : 0.0f;
     };
-    const bool reproject = !(a.opts & OPT_NO_REPROJECT);
     const bool use_blocks = !(a.opts & OPT_ROW_BY_ROW);
     const bool ind_blocks = use_blocks && !(a.opts & OPT_DEPENDENT_BLOCKS_ONLY);
     int64_t i = i0, applied = 0;
@@ -255,14 +286,12 @@ __global__ void __launch_bounds__(K::NT, K::OCC) k_push_mf(PushArgs<float> a, in
         asm volatile("" : "+v"(lane_l));
         const int li = lane_l & 15, lg = lane_l >> 4, tl = 64 * wv + lane_l;
         const int pk = tl >> 4, pj = tl & 15, pk15 = pk & 15;
-        // C[4s + g][16 (w + NW tau) + i] in FP64 (zero past the rank and past m)
-        auto cval = [&](int s, int tau) -> double {
-            if constexpr (K::CG) {
-                const int row = 4 * s + lg, col = 16 * (wv + NW * tau) + li;
-                return (row < r && col < m) ? (double)Cg[(size_t)row * ldm + col] : 0.0;
-            } else {
-                return f64_of(c[s][tau]);
-            }
+        // C[4s + g][16 ct + i] in FP64 from LDS (rows past the rank and columns
+        // past m are zero there; column tiles past MMAX read as zero)
+        auto cval = [&](int s, int ct) -> double {
+            if (ct >= NTT) return 0.0;
+            const int k = 4 * s + lg, col = 16 * ct + li;
+            return (double)sct[(size_t)k * MMAX + 4 * ((col >> 2) ^ (k & 15)) + (col & 3)];
         };
         if (block_mode) {
             // ================= block of up to KB rows =================
@@ -280,15 +309,13 @@ __global__ void __launch_bounds__(K::NT, K::OCC) k_push_mf(PushArgs<float> a, in
             pf_i = i + nblk;
             if (pf_i < i1) fetch_block(G0 + (pf_i - i0) * (int64_t)m, a.y + pf_i, (int)min((int64_t)KB, i1 - pf_i), m, tl, pfv, pfy);
 
-            // ---- G = Gamma_blk Ct^T: tiles u = wv + 4 ups of G^T ----
+            // ---- V = Gamma_blk C^T: tiles u = wv + NW ups of V^T ----
             const int nur = (r + 15) / 16;
-            // G^T tiles of the 16 rows held in x1f (block-row layout) against the Ct
-            // rows 16 u + i of this wave's tiles; returns this lane's part of the
-            // rows' squared norms
-            auto g_loop = [&](d4 (&gacc)[UPW]) -> double {
+            d4 gacc[UPW];
+            double gsq = 0.0;
+            {
 #pragma unroll
                 for (int ups = 0; ups < UPW; ++ups) gacc[ups] = (d4){0.0, 0.0, 0.0, 0.0};
-                double gsq = 0.0;
                 // chunk 4q + g of a row with (row & 15) == i sits at physical chunk (4q + g) ^ i;
                 // the operands of chunk q + 1 are loaded while chunk q is multiplied
                 const float *gbase = x1f + li * MMAX;
@@ -326,11 +353,56 @@ __global__ void __launch_bounds__(K::NT, K::OCC) k_push_mf(PushArgs<float> a, in
                         }
                     }
                 }
-                return gsq;
-            };
-            d4 gacc[UPW];
-            const double gsq = sum_rows(g_loop(gacc));  // ||Gamma_i||^2
-            double gwp = 0.0;     // this wave's part of (G w)_i
+            }
+            gsq = sum_rows(gsq);  // ||Gamma_i||^2
+#pragma unroll
+            for (int ups = 0; ups < UPW; ++ups) {
+                const int u = wv + NW * ups;
+                if (u < nur) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) x2[gpos<RMAX>(li, 16 * u + 4 * v + lg)] = gacc[ups][v];
+                }
+            }
+            double gi[TPW][4];  // Gamma_blk[i][16 tl + 4 v + g] for this wave's column tiles
+#pragma unroll
+            for (int tau = 0; tau < TPW; ++tau)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    gi[tau][v] = wv + NW * tau < NTT ? (double)x1f[li * MMAX + 4 * ((4 * (wv + NW * tau) + v) ^ li) + lg] : 0.0;
+            __syncthreads();
+
+            // ---- G^T = H^-1 V^T on this wave's row tiles (H^-1 symmetric) ----
+#pragma unroll
+            for (int ups = 0; ups < UPW; ++ups) {
+                const int u = wv + NW * ups;
+                gacc[ups] = (d4){0.0, 0.0, 0.0, 0.0};
+                if (u < nur) {
+                    if constexpr (K::HG) {
+                        // tiles of H^-1 from L2, the next one requested while the current one is multiplied
+                        d4 ht = hload(0, ups, r);
+#pragma unroll 1
+                        for (int u2 = 0; u2 < nur; ++u2) {
+                            const d4 hc = ht;
+                            if (u2 + 1 < nur) ht = hload(u2 + 1, ups, r);
+#pragma unroll
+                            for (int v = 0; v < 4; ++v)
+                                gacc[ups] = mma(hc[v], x2[gpos<RMAX>(li, 16 * u2 + 4 * v + lg)], gacc[ups]);
+                        }
+                    } else {
+#pragma unroll
+                        for (int u2 = 0; u2 < NU; ++u2) {
+                            if (u2 < nur) {
+                                const d4 ht = hload(u2, ups, r);
+#pragma unroll
+                                for (int v = 0; v < 4; ++v)
+                                    gacc[ups] = mma(ht[v], x2[gpos<RMAX>(li, 16 * u2 + 4 * v + lg)], gacc[ups]);
+                            }
+                        }
+                    }
+                }
+            }
+            __syncthreads();  // every read of V is done
+            double gwp = 0.0;  // this wave's part of (G w)_i
 #pragma unroll
             for (int ups = 0; ups < UPW; ++ups) {
                 const int u = wv + NW * ups;
@@ -343,57 +415,23 @@ __global__ void __launch_bounds__(K::NT, K::OCC) k_push_mf(PushArgs<float> a, in
                 }
             }
             gwp = sum_rows(gwp);
-            double gi[TPW][4];  // Gamma_blk[i][16 tl + 4 v + g] for this wave's column tiles
-#pragma unroll
-            for (int tau = 0; tau < TPW; ++tau)
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    gi[tau][v] = wv + NW * tau < NTT ? (double)x1f[li * MMAX + 4 * ((4 * (wv + NW * tau) + v) ^ li) + lg] : 0.0;
             __syncthreads();
 
-            // ---- R^T = Gamma_blk^T - C^T G^T and ||R_i||^2 ----
+            // ---- R^T = Gamma_blk^T - C^T G^T, ||R_i||^2 and this wave's part of R R^T ----
             double rsq = 0.0;
+            d4 sacc_r = (d4){0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int tau = 0; tau < TPW; ++tau) {
-                if (wv + NW * tau < nq) {
+                const int ct = wv + NW * tau;
+                if (ct < nq) {
                     d4 d = (d4){gi[tau][0], gi[tau][1], gi[tau][2], gi[tau][3]};
-                    if constexpr (K::CG) {
-                        // C from global memory: the loads of row tile u2 + 3 are issued
-                        // while the products of row tile u2 run
-                        const int col = 16 * (wv + NW * tau) + li;
-                        const float *cb = Cg + (col < m ? col : 0);
-                        const int rlim = col < m ? r : 0;
-                        float b0[4], b1[4], b2[4];
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) {
-                            const int row = 4 * v + lg;
-                            b0[v] = row < rlim ? cb[(size_t)row * ldm] : 0.0f;
-                            b1[v] = row + 16 < rlim ? cb[(size_t)(row + 16) * ldm] : 0.0f;
-                            b2[v] = row + 32 < rlim ? cb[(size_t)(row + 32) * ldm] : 0.0f;
-                        }
+                    if constexpr (K::HG) {
 #pragma unroll 1
-                        for (int u2 = 0; u2 < nur; u2 += 3) {
+                        for (int u2 = 0; u2 < nur; ++u2) {
 #pragma unroll
                             for (int v = 0; v < 4; ++v) {
-                                const int row = 16 * u2 + 4 * v + lg;
-                                d = mma((double)b0[v], -x2[gpos<RMAX>(li, row)], d);
-                                b0[v] = row + 48 < rlim ? cb[(size_t)(row + 48) * ldm] : 0.0f;
-                            }
-                            if (u2 + 1 < nur) {
-#pragma unroll
-                                for (int v = 0; v < 4; ++v) {
-                                    const int row = 16 * u2 + 16 + 4 * v + lg;
-                                    d = mma((double)b1[v], -x2[gpos<RMAX>(li, row)], d);
-                                    b1[v] = row + 48 < rlim ? cb[(size_t)(row + 48) * ldm] : 0.0f;
-                                }
-                            }
-                            if (u2 + 2 < nur) {
-#pragma unroll
-                                for (int v = 0; v < 4; ++v) {
-                                    const int row = 16 * u2 + 32 + 4 * v + lg;
-                                    d = mma((double)b2[v], -x2[gpos<RMAX>(li, row)], d);
-                                    b2[v] = row + 48 < rlim ? cb[(size_t)(row + 48) * ldm] : 0.0f;
-                                }
+                                const int s = 4 * u2 + v;
+                                d = mma(cval(s, ct), -x2[gpos<RMAX>(li, 4 * s + lg)], d);
                             }
                         }
                     } else {
@@ -403,12 +441,14 @@ __global__ void __launch_bounds__(K::NT, K::OCC) k_push_mf(PushArgs<float> a, in
 #pragma unroll
                             for (int v = 0; v < 4; ++v) {
                                 const int s = 4 * u2 + v;
-                                d = mma(cval(s, tau), -x2[gpos<RMAX>(li, 4 * s + lg)], d);
+                                d = mma(cval(s, ct), -x2[gpos<RMAX>(li, 4 * s + lg)], d);
                             }
                         }
                     }
                     }
                     rsq += d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + d[3] * d[3];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) sacc_r = mma(d[v], d[v], sacc_r);
                 }
             }
             rsq = sum_rows(rsq);
@@ -468,69 +508,8 @@ __global__ void __launch_bounds__(K::NT, K::OCC) k_push_mf(PushArgs<float> a, in
             d4 z[UPW];
             d4 sacc = (d4){0.0, 0.0, 0.0, 0.0};
             if (indblk) {
-                // ---- independent rows: R (twice projected) and R R^T ----
-                // R = Gamma_blk - G C with the rows read again from global memory and G
-                // from X2; stored in FP32 to x1f (block-row layout) or to Ct rows r0 + i
-                // (i < nst), which are zero and become the new rows; with gram, this
-                // wave's part of R R^T is accumulated into sacc (result layout)
-                auto r_pass = [&](bool to_ct, bool gram) {
-#pragma unroll
-                    for (int tau = 0; tau < TPW; ++tau) {
-                        const int ct = wv + NW * tau;
-                        if (ct < nq) {
-                            d4 d;
-#pragma unroll
-                            for (int v = 0; v < 4; ++v) {
-                                const int col = 16 * ct + 4 * v + lg;
-                                d[v] = (li < nblk && col < m) ? (double)G0[(i - i0 + li) * (int64_t)m + col] : 0.0;
-                            }
-#pragma unroll
-                            for (int u2 = 0; u2 < NU; ++u2) {
-                                if (u2 < nur) {
-#pragma unroll
-                                    for (int v = 0; v < 4; ++v) {
-                                        const int s = 4 * u2 + v;
-                                        d = mma(cval(s, tau), -x2[gpos<RMAX>(li, 4 * s + lg)], d);
-                                    }
-                                }
-                            }
-#pragma unroll
-                            for (int v = 0; v < 4; ++v) {
-                                const int c4 = 4 * ct + v;
-                                if (!to_ct) {
-                                    x1f[li * MMAX + 4 * (c4 ^ li) + lg] = (float)d[v];
-                                } else if (li < nst) {
-                                    const int k = r0 + li;
-                                    sct[(size_t)k * MMAX + 4 * (c4 ^ (k & 15)) + lg] = (float)d[v];
-                                }
-                            }
-                            if (gram) {
-#pragma unroll
-                                for (int v = 0; v < 4; ++v) sacc = mma(d[v], d[v], sacc);
-                            }
-                        }
-                    }
-                };
-#pragma unroll
-                for (int ups = 0; ups < UPW; ++ups) z[ups] = (d4){0.0, 0.0, 0.0, 0.0};
-                __syncthreads();  // the rank test's reads of X1 are done
-                if (reproject && r0 > 0) {
-                    // second projection ("twice is enough"): G += R1 Ct^T
-                    r_pass(false, false);
-                    __syncthreads();
-                    d4 g2acc[UPW];
-                    (void)g_loop(g2acc);
-#pragma unroll
-                    for (int ups = 0; ups < UPW; ++ups) {
-                        const int u = wv + NW * ups;
-                        if (u < nur) {
-#pragma unroll
-                            for (int v = 0; v < 4; ++v) x2[gpos<RMAX>(li, 16 * u + 4 * v + lg)] += g2acc[ups][v];
-                        }
-                    }
-                    __syncthreads();
-                }
-                r_pass(true, true);
+                // independent rows: the Gram matrix R R^T of the rejections
+                sacc = sacc_r;
             } else {
             // ---- Z = P^-1 G^T and this wave's part of S = I + G Z ----
 #pragma unroll
@@ -640,10 +619,10 @@ __global__ void __launch_bounds__(K::NT, K::OCC) k_push_mf(PushArgs<float> a, in
 #pragma unroll
                     for (int q = 0; q < CBW; ++q)
 #pragma unroll
-                        for (int h = kb / 2; h < 8; ++h) {
-                            const double2 v2 = reinterpret_cast<const double2 *>(col + 16 * q)[h];
-                            pc[q][2 * h] = v2.x;
-                            pc[q][2 * h + 1] = v2.y;
+                        for (int h2 = kb / 2; h2 < 8; ++h2) {
+                            const double2 v2 = reinterpret_cast<const double2 *>(col + 16 * q)[h2];
+                            pc[q][2 * h2] = v2.x;
+                            pc[q][2 * h2 + 1] = v2.y;
                         }
 #pragma unroll
                     for (int q = 0; q < CBW; ++q) cyv[q] = col[16 * CBW + kb + q];
@@ -729,15 +708,11 @@ __global__ void __launch_bounds__(K::NT, K::OCC) k_push_mf(PushArgs<float> a, in
                         }
                         wc[j] = j < ni ? (a0 + a1) * x1[K::X1_C + 16 + j] : 0.0;
                     }
-                    // M = W^T W = (R R^T)^-1 on the first ni rows, in the result layout
-                    d4 macc = (d4){0.0, 0.0, 0.0, 0.0};
+                    // W row-major: W[j][i] at X1_W + 16 j + i (the records are read by now)
+                    if (lg == 0) {
 #pragma unroll
-                    for (int ks = 0; ks < 4; ++ks) {
-                        const double av = lg == 0 ? wc[4 * ks] : lg == 1 ? wc[4 * ks + 1] : lg == 2 ? wc[4 * ks + 2] : wc[4 * ks + 3];
-                        macc = mma(av, av, macc);
+                        for (int j = 0; j < 16; ++j) x1[K::X1_W + 16 * j + li] = wc[j];
                     }
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) x1[K::X1_M + 16 * (4 * v + lg) + li] = macc[v];
                     if (li == 0 && lg == 0) {
                         x1[K::X1_COL] = (double)ni;
                         x1[K::X1_COL + 1] = ((badm >> ni) & 1ull) ? 1.0 : 0.0;
@@ -757,70 +732,89 @@ __global__ void __launch_bounds__(K::NT, K::OCC) k_push_mf(PushArgs<float> a, in
             }
             __syncthreads();
             if (indblk) {
-                // ---- independent rows 0 .. ni-1 of the block: K = M R, Ct -= G^T K ----
+                // ---- independent rows 0 .. ni-1 of the block: H^-1 += U U^T with
+                //      U = [G^T W^T; -W^T], appends to C, P^-1 and w ----
                 const int ni = (int)x1[K::X1_COL];
                 const bool nonf = x1[K::X1_COL + 1] != 0.0;
                 if (ni == 0) {
-                    // the first row failed the test on its twice-projected rejection: clear
-                    // the rows of Ct that held R and take the row alone
-                    for (int idx = t; idx < nst * CH; idx += K::NT) {
-                        const int k = r0 + idx / CH, cc = idx % CH;
-                        *reinterpret_cast<float4 *>(sct + (size_t)k * MMAX + 4 * cc) = make_float4(0.f, 0.f, 0.f, 0.f);
-                    }
+                    // the first row failed the pivot test although its rejection passed
+                    // the row test (the two sums round differently): take it alone
                     block_mode = false;
                     ring_ok = false;
                     continue;
                 }
-                const int nur0 = nur;
+                const int nurn = (r0 + ni + 15) / 16;
+                // Q = G^T W^T on this wave's row tiles: A = G^T[16u + i][4ks + g],
+                // B = W^T[4ks + g][i] = W[i][4ks + g]
+                d4 q[UPW];
 #pragma unroll
-                for (int tau = 0; tau < TPW; ++tau) {
-                    const int ct = wv + NW * tau;
-                    if (ct < nq) {
-                        // column 16 ct + i: float4 chunk cq, element ce
-                        const int cq = 4 * ct + (li >> 2), ce = li & 3;
-                        // K[4v + g][16 ct + i] = sum_j M[4v + g][j] R[j][16 ct + i]; each lane
-                        // reads and then rewrites the same four elements of rows r0 + 4 ks + g
-                        double bk[4];
+                for (int ups = 0; ups < UPW; ++ups) {
+                    const int u = wv + NW * ups;
+                    q[ups] = (d4){0.0, 0.0, 0.0, 0.0};
+                    if (u < nurn) {
 #pragma unroll
                         for (int ks = 0; ks < 4; ++ks) {
-                            const int j = 4 * ks + lg, k = r0 + j;
-                            bk[ks] = j < ni ? (double)sct[(size_t)k * MMAX + 4 * (cq ^ (k & 15)) + ce] : 0.0;
+                            const int j = 4 * ks + lg;
+                            const double ga = j < ni ? x2[gpos<RMAX>(j, 16 * u + li)] : 0.0;
+                            q[ups] = mma(ga, x1[K::X1_W + 16 * li + j], q[ups]);
                         }
-                        d4 kt = (d4){0.0, 0.0, 0.0, 0.0};
+                    }
+                }
+                __syncthreads();  // every read of G is done
+                // U to X2: rows kk < r0 are Q, rows r0 .. r0 + ni - 1 are -W^T
 #pragma unroll
-                        for (int ks = 0; ks < 4; ++ks) kt = mma(x1[K::X1_M + 16 * (4 * ks + lg) + li], bk[ks], kt);
+                for (int ups = 0; ups < UPW; ++ups) {
+                    const int u = wv + NW * ups;
+                    if (u < nurn) {
 #pragma unroll
                         for (int v = 0; v < 4; ++v) {
-                            const int j = 4 * v + lg, k = r0 + j;
-                            if (j >= ni) kt[v] = 0.0;
-                            if (j < nst) sct[(size_t)k * MMAX + 4 * (cq ^ (k & 15)) + ce] = (float)kt[v];
+                            const int kk = 16 * u + 4 * v + lg;
+                            const double val = kk < r0 ? q[ups][v]
+                                                       : (kk < r0 + ni ? -x1[K::X1_W + 16 * li + (kk - r0)] : 0.0);
+                            x2[zpos(kk, li)] = val;
                         }
-                        // Ct[k][16 ct + i] -= sum_j G[j][k] K[j][16 ct + i] for k < r0; kt[ks]
-                        // is the B operand K[4 ks + g][16 ct + i]
+                    }
+                }
+                // rows r0 .. r0 + ni - 1 of C: the raw block rows
+                for (int idx = t; idx < ni * CH; idx += K::NT) {
+                    const int j = idx / CH, cc = idx - j * CH, k = r0 + j;
+                    const float *src = G0 + (i - i0 + j) * (int64_t)m;
+                    float v[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) v[e] = 4 * cc + e < m ? src[4 * cc + e] : 0.0f;
+                    *reinterpret_cast<float4 *>(sct + (size_t)k * MMAX + 4 * (cc ^ (k & 15))) =
+                        make_float4(v[0], v[1], v[2], v[3]);
+                }
+                __syncthreads();
+#pragma unroll
+                for (int ups = 0; ups < UPW; ++ups) {
+                    const int u = wv + NW * ups;
+                    if (u < nurn) {
+                        double bt[4];
+#pragma unroll
+                        for (int ks = 0; ks < 4; ++ks) bt[ks] = x2[zpos(16 * u + li, 4 * ks + lg)];
+                        if constexpr (K::HG) {
 #pragma unroll 1
-                        for (int u = 0; u < nur0; ++u) {
-                            d4 acc;
+                            for (int u2 = 0; u2 < nurn; ++u2) {
+                                d4 acc = hload(u2, ups, r0);
 #pragma unroll
-                            for (int v = 0; v < 4; ++v) {
-                                const int k = 16 * u + 4 * v + lg;
-                                acc[v] = k < r0 ? (double)sct[(size_t)k * MMAX + 4 * (cq ^ (k & 15)) + ce] : 0.0;
+                                for (int ks = 0; ks < 4; ++ks) acc = mma(x2[zpos(16 * u2 + li, 4 * ks + lg)], bt[ks], acc);
+                                hstore(u2, ups, acc, r0 + ni);
                             }
+                        } else {
 #pragma unroll
-                            for (int ks = 0; ks < 4; ++ks) {
-                                const int j = 4 * ks + lg;
-                                const double ga = j < ni ? x2[gpos<RMAX>(j, 16 * u + li)] : 0.0;
-                                acc = mma(-ga, kt[ks], acc);
-                            }
+                            for (int u2 = 0; u2 < NU; ++u2) {
+                                if (u2 < nurn) {
+                                    d4 acc = hload(u2, ups, r0);
 #pragma unroll
-                            for (int v = 0; v < 4; ++v) {
-                                const int k = 16 * u + 4 * v + lg;
-                                if (k < r0) sct[(size_t)k * MMAX + 4 * (cq ^ (k & 15)) + ce] = (float)acc[v];
+                                    for (int ks = 0; ks < 4; ++ks) acc = mma(x2[zpos(16 * u2 + li, 4 * ks + lg)], bt[ks], acc);
+                                    hstore(u2, ups, acc, r0 + ni);
+                                }
                             }
                         }
                     }
                 }
-                // appends: rows r0 .. r0 + ni - 1 of C (the raw rows), P^-1 = 1 on the
-                // diagonal, w = y (Theorem 4 in coordinates)
+                // appends: P^-1 = 1 on the new diagonal, w = y (Theorem 4 in coordinates)
 #pragma unroll
                 for (int ups = 0; ups < UPW; ++ups) {
                     const int u = wv + NW * ups;
@@ -834,21 +828,6 @@ __global__ void __launch_bounds__(K::NT, K::OCC) k_push_mf(PushArgs<float> a, in
                             if (row == colp && row >= r0 && row < r0 + ni) p[u2][ups][v] = 1.0;
                         }
                     }
-                }
-                if constexpr (K::CG) {
-                    for (int idx = t; idx < ni * m; idx += K::NT) {
-                        const int j = idx / m, col = idx - j * m;
-                        Cg[(size_t)(r0 + j) * ldm + col] = G0[(i - i0 + j) * (int64_t)m + col];
-                    }
-                } else {
-#pragma unroll
-                    for (int s = 0; s < 4 * NU; ++s)
-#pragma unroll
-                        for (int tau = 0; tau < TPW; ++tau) {
-                            const int row = 4 * s + lg, col = 16 * (wv + NW * tau) + li;
-                            if (row >= r0 && row < r0 + ni && wv + NW * tau < NTT)
-                                c[s][tau] = col < m ? G0[(i - i0 + row - r0) * (int64_t)m + col] : 0.0f;
-                        }
                 }
                 r = r0 + ni;
                 i += ni;
@@ -967,15 +946,16 @@ __global__ void __launch_bounds__(K::NT, K::OCC) k_push_mf(PushArgs<float> a, in
         const double yv = (double)y_next;
         if (i + 1 < i1) y_next = a.y[i + 1];
         const float *gcur = sg_ring + cur * MMAX;
-        double *sgam = x1 + K::X1_GAM, *szeta = x1 + K::X1_ZETA, *sred = x1 + K::X1_RED, *sgr = x1 + K::X1_GR;
+        double *sgam = x1 + K::X1_GAM, *szeta = x1 + K::X1_ZETA, *sv = x1 + K::X1_V;
+        double *sred = x1 + K::X1_RED, *sgr = x1 + K::X1_GR;
 
-        // ---- A: gamma = Ct Gamma (rows k = pk + 16 b, 16-lane sums) ----
+        // ---- A: v = C Gamma (rows k = pk + RS b, 16-lane sums) ----
         double gam[NB];
 #pragma unroll
         for (int b = 0; b < NB; ++b) gam[b] = 0.0;
 #pragma unroll 1
         for (int c4 = 0; c4 < cba4; ++c4) {
-            const int ph = 16 * c4 + pj, lc = ph ^ pk15;  // physical chunk of Ct rows k (k & 15 == pk & 15), logical chunk
+            const int ph = 16 * c4 + pj, lc = ph ^ pk15;  // physical chunk of C rows k (k & 15 == pk & 15), logical chunk
             const float4 gv = *reinterpret_cast<const float4 *>(gcur + 4 * lc);
             const double g0 = gv.x, g1 = gv.y, g2v = gv.z, g3 = gv.w;
 #pragma unroll
@@ -992,12 +972,43 @@ __global__ void __launch_bounds__(K::NT, K::OCC) k_push_mf(PushArgs<float> a, in
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             gam[b] = sum16(gam[b]);
-            if (pj == 0) sgam[pk + RS * b] = gam[b];
+            if (pj == 0) sv[pk + RS * b] = gam[b];
+        }
+        __syncthreads();
+
+        // ---- A2: gamma = H^-1 v per column tile, one reduce-scatter ----
+        const int nur = (r + 15) / 16;
+        {
+            double hacc[2] = {0.0, 0.0};
+            if constexpr (K::HG) {
+#pragma unroll 1
+                for (int u2 = 0; u2 < nur; ++u2) {
+#pragma unroll
+                    for (int ups = 0; ups < UPW; ++ups) {
+                        const d4 ht = hload(u2, ups, r);
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) hacc[ups] += ht[v] * sv[16 * u2 + 4 * v + lg];
+                    }
+                }
+            } else {
+#pragma unroll
+            for (int u2 = 0; u2 < NU; ++u2) {
+                if (u2 < nur) {
+#pragma unroll
+                    for (int ups = 0; ups < UPW; ++ups) {
+                        const d4 ht = hload(u2, ups, r);
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) hacc[ups] += ht[v] * sv[16 * u2 + 4 * v + lg];
+                    }
+                }
+            }
+            }
+            const double tg = scatter4(hacc[0], hacc[1], 0.0, 0.0);  // gamma[16 (w + NW g) + i] on lane group g < UPW
+            if (lg < UPW) sgam[16 * (wv + NW * lg) + li] = tg;
         }
         __syncthreads();
 
         // ---- B: C^T gamma, zeta = P^-1 gamma, gamma^T w per column tile ----
-        const int nur = (r + 15) / 16;
         double acc[4] = {0.0, 0.0, 0.0, 0.0}, zacc[2] = {0.0, 0.0};
 #pragma unroll
         for (int u2 = 0; u2 < NU; ++u2) {
@@ -1007,7 +1018,7 @@ __global__ void __launch_bounds__(K::NT, K::OCC) k_push_mf(PushArgs<float> a, in
                     const int s = 4 * u2 + v;
                     const double gs = sgam[4 * s + lg];
 #pragma unroll
-                    for (int tau = 0; tau < TPW; ++tau) acc[tau] += cval(s, tau) * gs;
+                    for (int tau = 0; tau < TPW; ++tau) acc[tau] += cval(s, wv + NW * tau) * gs;
 #pragma unroll
                     for (int ups = 0; ups < UPW; ++ups) zacc[ups] += p[u2][ups][v] * gs;
                 }
@@ -1074,94 +1085,39 @@ __global__ void __launch_bounds__(K::NT, K::OCC) k_push_mf(PushArgs<float> a, in
                 flags |= FLAG_RANK_CAPACITY;
                 break;
             }
-            double s_use = sp;
-            if (reproject && r > 0) {
-                // second pass ("twice is enough"): gamma2 = Ct Gamma_r, Gamma_r -= C^T gamma2
-                double gam2[NB];
+            // H^-1 <- [[H^-1 + gamma gamma^T / s, -gamma / s], [-gamma^T / s, 1 / s]]
+            const double inv_s = 1.0 / sp;
+            // tile (u2, u) of the bordered H^-1
+            auto border = [&](int u2, int ups) {
+                const int colh = 16 * (wv + NW * ups) + li;
+                const double gcol = colh < r ? sgam[colh] : 0.0;
+                d4 ht = hload(u2, ups, r);
 #pragma unroll
-                for (int b = 0; b < NB; ++b) gam2[b] = 0.0;
+                for (int v = 0; v < 4; ++v) {
+                    const int row = 16 * u2 + 4 * v + lg;
+                    const double grow = row < r ? sgam[row] : 0.0;
+                    if (row < r && colh < r) ht[v] += (grow * gcol) * inv_s;
+                    else if (row < r && colh == r) ht[v] = -grow * inv_s;
+                    else if (row == r && colh < r) ht[v] = -gcol * inv_s;
+                    else if (row == r && colh == r) ht[v] = inv_s;
+                }
+                hstore(u2, ups, ht, r + 1);
+            };
+#pragma unroll
+            for (int ups = 0; ups < UPW; ++ups) {
+                if constexpr (K::HG) {
 #pragma unroll 1
-                for (int c4 = 0; c4 < cba4; ++c4) {
-                    const int ph = 16 * c4 + pj, lc = ph ^ pk15;
-                    const double r0 = sgr[4 * lc], r1 = sgr[4 * lc + 1], r2 = sgr[4 * lc + 2], r3 = sgr[4 * lc + 3];
+                    for (int u2 = 0; 16 * u2 <= r; ++u2) border(u2, ups);
+                } else {
 #pragma unroll
-                    for (int b = 0; b < NB; ++b) {
-                        const int k = pk + RS * b;
-                        float4 v = *reinterpret_cast<const float4 *>(sct + (size_t)min(k, ra - 1) * MMAX + 4 * ph);
-                        if (k >= ra) v = make_float4(0.f, 0.f, 0.f, 0.f);
-                        gam2[b] += (double)v.x * r0 + (double)v.y * r1 + (double)v.z * r2 + (double)v.w * r3;
-                    }
-                }
-                // every read of sgam (zeta, gamma^T w) ended before the last barrier
-#pragma unroll
-                for (int b = 0; b < NB; ++b) {
-                    gam2[b] = sum16(gam2[b]);
-                    if (pj == 0) sgam[pk + RS * b] = gam2[b];
-                    gam[b] += gam2[b];
-                }
-                __syncthreads();
-                double acc2[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int u2 = 0; u2 < NU; ++u2) {
-                    if (u2 < nur) {
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) {
-                            const int s = 4 * u2 + v;
-                            const double gs = sgam[4 * s + lg];
-#pragma unroll
-                            for (int tau = 0; tau < TPW; ++tau) acc2[tau] += cval(s, tau) * gs;
-                        }
-                    }
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-                const double tcol2 = scatter4(acc2[0], acc2[1], acc2[2], acc2[3]);
-                double sp2 = 0.0, u0 = 0.0, u1 = 0.0, u3 = 0.0;
-                if (lg < TPW && wv + NW * lg < NTT) {
-                    const int col = 16 * (wv + NW * lg) + li;
-                    const double v = sgr[col] - tcol2;
-                    sgr[col] = v;
-                    sp2 = v * v;
-                }
-                block_sum4<NW>(sp2, u0, u1, u3, sred);
-                s_use = sp2;
-            }
-            const double inv_s = 1.0 / s_use;
-            // Ct <- Ct - gamma K^T on rows k < r (K = Gamma_r / ||Gamma_r||^2)
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                const int k = pk + RS * b;
-                if (k < r) {
-                    const float gb = (float)gam[b];
-#pragma unroll 1
-                    for (int c4 = 0; c4 < cba4; ++c4) {
-                        const int ph = 16 * c4 + pj, lc = ph ^ pk15;
-                        float4 *p4 = reinterpret_cast<float4 *>(sct + (size_t)k * MMAX + 4 * ph);
-                        float4 v = *p4;
-                        v.x = fmaf(-gb, (float)(sgr[4 * lc] * inv_s), v.x);
-                        v.y = fmaf(-gb, (float)(sgr[4 * lc + 1] * inv_s), v.y);
-                        v.z = fmaf(-gb, (float)(sgr[4 * lc + 2] * inv_s), v.z);
-                        v.w = fmaf(-gb, (float)(sgr[4 * lc + 3] * inv_s), v.w);
-                        *p4 = v;
-                    }
+                    for (int u2 = 0; u2 < NU; ++u2)
+                        if (16 * u2 <= r) border(u2, ups);
                 }
             }
-            // append: row r of Ct (K^T) and of C (Gamma^T), P^-1[r][r] = 1, w[r] = y
+            // append: row r of C (the raw row), P^-1[r][r] = 1, w[r] = y
             if (tl < CH) {
-                const float4 kv = make_float4((float)(sgr[4 * tl] * inv_s), (float)(sgr[4 * tl + 1] * inv_s),
-                                              (float)(sgr[4 * tl + 2] * inv_s), (float)(sgr[4 * tl + 3] * inv_s));
-                *reinterpret_cast<float4 *>(sct + (size_t)r * MMAX + 4 * (tl ^ (r & 15))) = kv;
-            }
-            if constexpr (K::CG) {
-                // row r of C straight to the state; the barrier below makes it visible
-                for (int j = tl; j < m; j += K::NT) Cg[(size_t)r * ldm + j] = gcur[j];
-            } else if (lg == (r & 3)) {
-#pragma unroll
-                for (int s = 0; s < 4 * NU; ++s)
-                    if (s == (r >> 2)) {
-#pragma unroll
-                        for (int tau = 0; tau < TPW; ++tau)
-                            if (wv + NW * tau < NTT) c[s][tau] = gcur[16 * (wv + NW * tau) + li];
-                    }
+                const float4 gv = *reinterpret_cast<const float4 *>(gcur + 4 * tl);
+                *reinterpret_cast<float4 *>(sct + (size_t)r * MMAX + 4 * (tl ^ (r & 15))) = gv;
             }
 #pragma unroll
             for (int ups = 0; ups < UPW; ++ups) {
@@ -1200,17 +1156,8 @@ __global__ void __launch_bounds__(K::NT, K::OCC) k_push_mf(PushArgs<float> a, in
             const float vv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
             for (int e = 0; e < 4; ++e)
-                if (4 * cc + e < m) Cg[(size_t)(rmax_w + k) * ldm_w + 4 * cc + e] = vv[e];
+                if (4 * cc + e < m) Cg[(size_t)k * ldm_w + 4 * cc + e] = vv[e];
         }
-    }
-    if constexpr (!K::CG) {
-#pragma unroll
-        for (int s = 0; s < 4 * NU; ++s)
-#pragma unroll
-            for (int tau = 0; tau < TPW; ++tau) {
-                const int row = 4 * s + lg_w, col = 16 * (wv + NW * tau) + li_w;
-                if (row < r && col < m) Cg[(size_t)row * ldm_w + col] = c[s][tau];
-            }
     }
 #pragma unroll
     for (int ups = 0; ups < UPW; ++ups) {
@@ -1220,7 +1167,10 @@ __global__ void __launch_bounds__(K::NT, K::OCC) k_push_mf(PushArgs<float> a, in
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int row = 16 * u2 + 4 * v + lg_w;
-                if (row < r && col < r) Pg[(size_t)row * rmax_w + col] = p[u2][ups][v];
+                if (row < r && col < r) {
+                    Pg[(size_t)row * rmax_w + col] = p[u2][ups][v];
+                    if constexpr (!K::HG) Hg[(size_t)row * rmax_w + col] = h[u2][ups][v];
+                }
             }
         if (li_w == 0) {
 #pragma unroll
@@ -1246,12 +1196,12 @@ size_t lds_bytes(int ra) {
 // Rows of Ct reserved in LDS: r_max rounded up to whole 16-row tiles.
 inline int rows16(int r_max) { return (r_max + 15) / 16 * 16; }
 
-using F0 = MF<64, 128, 4, false>;
-using F1 = MF<128, 128, 8, true>;
-using F2 = MF<64, 192, 4, false>;
-using F3 = MF<128, 192, 8, true>;
-using F4 = MF<64, 256, 4, false>;
-using F5 = MF<128, 256, 8, true>;
+using F0 = MF<64, 128, 4>;
+using F1 = MF<128, 128, 8>;
+using F2 = MF<64, 192, 4>;
+using F3 = MF<128, 192, 8>;
+using F4 = MF<64, 256, 4>;
+using F5 = MF<128, 256, 8>;
 
 template <class K>
 bool fits_k(int m, int r_max) {

@@ -521,6 +521,8 @@ int class_rmax(int cls) {
     return cls >= 3 ? mf_rmax(cls - 3) : 0;
 }
 
+bool class_factored(int cls) { return cls >= 3 && cls < RG_NUM_CLASSES; }
+
 bool class_fits(int cls, int m, int r_max) {
     switch (cls) {
         case 0: return fits<C0>(m, r_max);
@@ -567,12 +569,14 @@ int choose_class(int m, int r_max, int dtype) {
         if (rule.cls < 0) return -1;
         if (class_fits(rule.cls, m, r_max)) return rule.cls;
     }
-    // built-in: the smallest class that holds the stream
+    // built-in: the smallest blocked variant that holds the stream (factored
+    // dual basis); the row-by-row classes only where a rule asks for them
+    const int v = mf_choose(m, r_max);
+    if (v >= 0) return 3 + v;
     if (fits<C0>(m, r_max)) return 0;
     if (fits<C1>(m, r_max)) return 1;
     if (fits<C2>(m, r_max)) return 2;
-    const int v = mf_choose(m, r_max);
-    return v >= 0 ? 3 + v : -1;
+    return -1;
 }
 
 hipError_t prepare_class(int cls, int rows_alloc) {

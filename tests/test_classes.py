@@ -32,11 +32,24 @@ def test_class_rule_validation():
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("cls", [3, 5, 8, -1])
+@pytest.mark.parametrize("cls", [0, 1, 2, 3, 5, 8, -1])
 def test_forced_class_matches_oracle(cls):
     from paper_2106_11594_amd import rg
     from tests.gpu_util import run_batch
-    bt = W.batched(B=12, m_lo=16, m_hi=60, n_scale=0.3, dtype="f32", seed=5)
+    if cls in (0, 1, 2):
+        # the row-by-row classes hold r_max <= 12 (class 0): planted ranks 4..8
+        rng = np.random.default_rng(50 + cls)
+        streams, rs = [], []
+        for b in range(12):
+            m, r = int(rng.integers(16, 61)), int(rng.integers(4, 9))
+            A = W.lowrank_rows(rng, m, r, int(rng.integers(m, 4 * m)))
+            Y, _ = W.targets(rng, A)
+            streams.append((A, Y.astype(np.float32).astype(np.float64)))
+            rs.append(r)
+        ms, ns, row_ptr, a_off, A, Y = W.pack(streams, 1e-3, "f32")
+        bt = W.Batch(ms, np.array(rs, np.int32), ns, row_ptr, a_off, A, Y, 1e-3, "f32")
+    else:
+        bt = W.batched(B=12, m_lo=16, m_hi=60, n_scale=0.3, dtype="f32", seed=5)
     r_max = np.minimum(bt.ms, bt.rs + 4).astype(np.int32)
     if cls >= 0:
         assert all(rg.class_fits(cls, int(m), int(c)) for m, c in zip(bt.ms, r_max))

@@ -21,8 +21,8 @@ def _rel(x, xo):
 
 
 def _kappa_tol(C):
-    kap = float(np.linalg.cond(C)) if C.shape[0] else 1.0
-    return (1e-5 if kap <= 1e3 else 0.1 * kap * 2.0 ** -23), kap
+    from tests.gpu_util import f32_tol
+    return f32_tol(C, factored=True)
 
 
 def _solve(A, Y, r_max, flags=0, chunks=None):
@@ -198,11 +198,9 @@ def test_rows_either_side_of_the_rank_threshold(delta, indep):
           % (delta, r, rr, ro, kap, _rel(x, xo), _rel(xr, xo)), flush=True)
     assert f == fr == 0 and r == rr == ro
     assert (r > r0) == indep
-    # Rows 1e-2 from the span of the earlier ones raise kappa(C) to a few hundred;
-    # the FP32 state then carries the first-order error kappa 2^-23 (row by row
-    # it reaches about 2 kappa 2^-23, the block append about kappa 2^-24).
-    assert _rel(x, xo) <= max(1e-5, kap * 2.0 ** -23)
-    assert _rel(x, xo) <= 2.0 * _rel(xr, xo) + 1e-6
+    # Rows 1e-2 from the span of the earlier ones raise kappa(C) to a few
+    # hundred, well inside the range where the factored dual basis holds 1e-5.
+    assert _rel(x, xo) <= 1e-5 and _rel(xr, xo) <= 1e-5
 
 
 @pytest.mark.gpu

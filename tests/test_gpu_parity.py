@@ -5,12 +5,12 @@ Tolerances:
     bit), x within 1e-11 relative.  Both sides run Algorithm 1 in IEEE double;
     only summation order and the coordinate form x = Ct^T w differ, which moves
     x by a few ulps times the condition of the basis (kappa(C) <= ~1e3 here).
-  FP32 streams: same decisions (rank and C bit for bit: C holds raw input rows,
-    exactly representable), x within 1e-5 relative when kappa(C) <= 1e3 and
-    within 0.1 * kappa(C) * 2^-23 above that.  First-order perturbation of the
-    FP32-stored Ct and P^-1 (relative error ~2^-24 per element) moves x by
-    O(kappa(C) * 2^-23); the constant 0.1 is three times the worst ratio seen
-    in an FP64 emulation of the FP32 arithmetic over batched-workload streams.
+  FP32 streams (the blocked on-chip classes, dual basis in factored form
+    H^-1 C with H^-1 = (C C^T)^-1 in FP64): same decisions (rank and C bit
+    for bit: C holds raw input rows, exactly representable), x within
+    max(1e-5, kappa(C)^2 2^-52) relative (tests/gpu_util.f32_tol): the
+    projections are FP64 arithmetic on exact rows, perturbed by about
+    2^-52 kappa(C)^2, and x is rounded to FP32 on output.
 """
 import json
 import os
@@ -40,8 +40,8 @@ def _rel(a, b):
 
 
 def _f32_tol(C):
-    kap = np.linalg.cond(C) if C.shape[0] else 1.0
-    return (1e-5 if kap <= 1e3 else 0.1 * kap * EPS32), kap
+    from tests.gpu_util import f32_tol
+    return f32_tol(C, factored=True)
 
 
 def _single(A, Y, dtype, eps=None, r_max=None, chunks=None, flags=0):
