@@ -49,3 +49,12 @@ def f32_tol(C, factored=True):
     if factored:
         return max(1e-5, kap * kap * 2.0 ** -52), kap
     return (1e-5 if kap <= 1e3 else 0.1 * kap * EPS32), kap
+
+
+def factored(m, r_max):
+    """Whether a stream of m regressors and rank capacity r_max runs in a
+    blocked on-chip class (dual basis in factored form) under the default
+    placement; otherwise it runs in the generic kernel with an explicit FP32
+    dual basis."""
+    from paper_2106_11594_amd import rg
+    return any(rg.class_fits(c, int(m), int(r_max)) for c in range(3, rg.class_count()))
