@@ -3,9 +3,18 @@
 One step = reset every stream to the empty state, push all rows of the
 batched workload (B = 4096 independent streams, m ~ U{16..256},
 r ~ U{4..m/2}, n ~ U{m..8m}, FP32 state with FP64 rank decisions), and
-materialise every solution x_b.  Inputs are resident in HBM before the timed
-region.  The FP64 C oracle is then run on the same rows on the host cores
-(cpu_baseline) and every stream's x and rank are compared with it.
+materialise every solution x_b.  The step is captured once into a HIP graph
+and the timed region replays it (the eager time is reported beside it).
+Inputs are resident in HBM before the timed region.  The FP64 C oracle is
+then run on the same rows on the host cores (cpu_baseline) and every stream's
+x and rank are compared with it.
+
+Further objects on the same JSON line: the roofline of the dominant kernel
+class against the LDS peak measured on the device by the library's probe
+(and against the FP64 matrix-core peak), per-class launch times, the single
+streams (m = 64 FP64; m = 2048 FP64 and FP32; the m = 1024 stress stream),
+a run with a rank capacity that does not know the planted rank, the
+differentiable solve's backward and the recursive pseudoinverse.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -180,6 +189,125 @@ def pinv_track_leg(torch, rg, W, steps, warmup, B=256, n=256, m=64, r=16):
                          "frac": gbs / PEAK_HBM_GBS, "algorithmic_bytes": B * per}}
 
 
+def lds_peak(torch, rg, cus, reps=5, iters=400):
+    """LDS read bandwidth of the device (GB/s): the library's probe on 8
+    workgroups per CU, best of reps launches timed with HIP events."""
+    blocks = 8 * cus
+    out = torch.empty(blocks * rg.LDS_PROBE_THREADS, dtype=torch.float32, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    rg.probe_lds_read(out, blocks, iters, stream)  # warm-up
+    best = 0.0
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        nbytes = rg.probe_lds_read(out, blocks, iters, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        best = max(best, nbytes / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    return best, blocks, iters
+
+
+def sub_batch(bt, idx):
+    """The streams idx of batch bt, packed as a batch of their own."""
+    streams = [bt.stream(int(b)) for b in idx]
+    ms, ns, row_ptr, a_off, A, Y = W_pack(streams, bt.eps, bt.dtype, np.float32)
+    return ms, ns, row_ptr, a_off, A, Y
+
+
+def W_pack(streams, eps, dtype, store):
+    from paper_2106_11594_amd import workloads as W
+    return W.pack(streams, eps, dtype, store)
+
+
+def time_push(torch, h, A, Y, rp, ao, x, stream, steps, warmup):
+    """Mean ms of (reset + push) and of the whole step (reset + push +
+    solution), eager, with HIP events on the handle's stream."""
+    push, whole = [], []
+    for k in range(warmup + steps):
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record(stream)
+        h.reset()
+        h.push(A, Y, rp, ao)
+        e1.record(stream)
+        h.solution(x)
+        e2.record(stream)
+        torch.cuda.synchronize()
+        if k >= warmup:
+            push.append(e0.elapsed_time(e1))
+            whole.append(e0.elapsed_time(e2))
+    return float(np.mean(push)), float(np.mean(whole))
+
+
+def class_legs(torch, rg, bt, r_max, classes, stream, steps, warmup):
+    """Every kernel class of the placement on its own streams alone: a batch of
+    those streams, pushed from empty with HIP events around the push on the
+    handle's stream.  Returns {class: {...}} with the algorithmic flops and
+    state bytes of the SURVEY model for those streams."""
+    out = {}
+    for c in sorted(set(int(v) for v in classes)):
+        idx = np.nonzero(classes == c)[0]
+        ms, ns, row_ptr, a_off, A, Y = sub_batch(bt, idx)
+        dev = torch.device("cuda:0")
+        Ad = torch.from_numpy(A).to(dev)
+        Yd = torch.from_numpy(Y).to(dev)
+        rp = torch.from_numpy(row_ptr).to(dev)
+        ao = torch.from_numpy(a_off).to(dev)
+        with torch.cuda.stream(stream):
+            h = rg.Batch(ms, r_max=r_max[idx], dtype="f32", eps=1e-3, stream=stream)
+            h.plan(ns)
+            x = torch.empty(h.n_x, dtype=torch.float32, device=dev)
+            push_ms, _ = time_push(torch, h, Ad, Yd, rp, ao, x, stream, steps, warmup)
+        assert (h.classes() == c).all()
+        flops, byts = model(ms, bt.rs[idx], ns)
+        shape = rg.class_info(c) if c >= 0 else (None, None, 256)
+        out[c] = {"streams": int(idx.size), "rows": int(ns.sum()), "launch_ms": push_ms,
+                  "algorithmic_flops": flops, "algorithmic_state_bytes": byts,
+                  "r_max_cap": shape[0], "m_cap": shape[1], "threads": shape[2]}
+        h.close()
+        del Ad, Yd
+    return out
+
+
+def single_leg(torch, rg, name, s, dtype, golden=None, steps=1, warmup=1):
+    """One stream pushed from empty (reset + push + solution), timed with HIP
+    events on the handle's stream; the rank and x compared with the oracle
+    (run here for the small stream, else the stored oracle result)."""
+    td = torch.float64 if dtype == "f64" else torch.float32
+    dev = torch.device("cuda:0")
+    A = torch.from_numpy(np.ascontiguousarray(s.A)).to(dev, td)
+    Y = torch.from_numpy(np.ascontiguousarray(s.Y)).to(dev, td)
+    n, m = s.A.shape
+    stream = torch.cuda.current_stream()
+    h = rg.Solver(m, dtype=dtype, eps=s.eps)
+    x = torch.empty(m, dtype=td, device=dev)
+    ts = []
+    for k in range(warmup + steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        h.reset()
+        h.push_rows(A, Y)
+        h.solution(x)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if k >= warmup:
+            ts.append(e0.elapsed_time(e1))
+    ms_ = float(np.mean(ts))
+    rank, flags = h.rank(), h.flags()
+    xg = x.double().cpu().numpy()
+    h.close()
+    esz = 8 if dtype == "f64" else 4
+    flops, byts = model(np.array([m]), np.array([rank]), np.array([n]), s=esz, s_in=esz)
+    rec = {"workload": name, "dtype": dtype, "rows": n, "ms": ms_, "us_per_row": 1e3 * ms_ / n,
+           "row_updates_per_s": n / (ms_ * 1e-3), "rank": rank, "flags": int(flags),
+           "algorithmic_state_bytes": byts, "state_bytes_rate_GBs": byts / (ms_ * 1e-3) / 1e9}
+    if golden is not None:
+        xo, ro = golden
+        rec["oracle_rank"] = int(ro)
+        rec["rel_err_vs_oracle"] = float(np.linalg.norm(xg - xo) / np.linalg.norm(xo))
+    del A, Y
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,10 +316,16 @@ def main():
     ap.add_argument("--B", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
     ap.add_argument("--serial-classes", action="store_true", help="launch size classes one after another")
+    ap.add_argument("--one-wg-per-stream", action="store_true",
+                    help="blocked classes with one workgroup per stream instead of the persistent grid")
     ap.add_argument("--default-classes", action="store_true",
                     help="ignore the autotuned class rules (paper_2106_11594_amd/class_rules.json)")
+    ap.add_argument("--no-graph", action="store_true", help="time eager launches only")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiable-solve (backward) leg")
     ap.add_argument("--no-pinv-track", action="store_true", help="skip the recursive pseudoinverse leg")
+    ap.add_argument("--no-single", action="store_true", help="skip the single-stream legs")
+    ap.add_argument("--no-classes", action="store_true", help="skip the per-class legs")
+    ap.add_argument("--no-capacity", action="store_true", help="skip the rank-unaware capacity leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the timed steps, run a plain copy kernel (out = -in) over MIB MiB twice, as the "
                          "reference point for HBM byte counters")
@@ -209,6 +343,7 @@ def main():
     print("generated %d streams, %d rows in %.1fs" % (bt.B, int(bt.ns.sum()), time.time() - t0),
           file=sys.stderr, flush=True)
     dev = torch.device("cuda:0")
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
     A = torch.from_numpy(bt.A).to(dev)
     Y = torch.from_numpy(bt.Y).to(dev)
     rp = torch.from_numpy(bt.row_ptr).to(dev)
@@ -218,47 +353,48 @@ def main():
     rules = None if args.default_classes else autotune.load()
     if rules:
         rg.set_class_rules(rules)
-    h = rg.Batch(bt.ms, r_max=r_max, dtype="f32", eps=1e-3,
-                 flags=rg.OPT_SERIAL_CLASSES if args.serial_classes else 0)
-    h.plan(bt.ns)
-    x = torch.empty(h.n_x, dtype=torch.float32, device=dev)
-    stream = torch.cuda.current_stream()
-
-    def step(ev=None):
-        h.reset()
-        if ev is not None:
-            ev[0].record(stream)
-        h.push(A, Y, rp, ao)
-        if ev is not None:
-            ev[1].record(stream)
-        h.solution(x)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    print("warmup done", file=sys.stderr, flush=True)
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_host = time.perf_counter()
-    start.record(stream)
-    for k in range(args.steps):
-        step(evs[k])
-    stop.record(stream)
-    t_host = (time.perf_counter() - t_host) / args.steps
-    torch.cuda.synchronize()
-    ms_step = start.elapsed_time(stop) / args.steps
-    push_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    flags = (rg.OPT_SERIAL_CLASSES if args.serial_classes else 0) | \
+        (rg.OPT_ONE_WG_PER_STREAM if args.one_wg_per_stream else 0)
+    stream = torch.cuda.Stream()  # default priority; the handle enqueues here and the graph captures it
+    with torch.cuda.stream(stream):
+        h = rg.Batch(bt.ms, r_max=r_max, dtype="f32", eps=1e-3, flags=flags, stream=stream)
+        h.plan(bt.ns)
+        x = torch.empty(h.n_x, dtype=torch.float32, device=dev)
     rows = int(bt.ns.sum())
+
+    # eager: reset + push + solution per step, events around the push
+    with torch.cuda.stream(stream):
+        t_host = time.perf_counter()
+        push_ms, eager_ms = time_push(torch, h, A, Y, rp, ao, x, stream, args.steps, args.warmup)
+        t_host = (time.perf_counter() - t_host) / (args.steps + args.warmup)
+    print("eager: %.3f ms/step, push %.3f ms" % (eager_ms, push_ms), file=sys.stderr, flush=True)
+
+    # graph: the same step captured once, replayed
+    ms_step, launch = eager_ms, "eager launches"
+    if not args.no_graph:
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            h.reset()
+            h.push(A, Y, rp, ao)
+            h.solution(x)
+        for _ in range(args.warmup):
+            g.replay()
+        torch.cuda.synchronize()
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        for _ in range(args.steps):
+            g.replay()
+        stop.record(stream)
+        torch.cuda.synchronize()
+        ms_step = start.elapsed_time(stop) / args.steps
+        launch = "one captured hipGraph replay per step (reset, push, solution)"
+        print("graph replay: %.3f ms/step" % ms_step, file=sys.stderr, flush=True)
     value = rows / (ms_step / 1e3)
-    print("timed %d steps: %.3f ms/step, push %.3f ms, host enqueue %.3f ms/step" % (args.steps, ms_step, push_ms, 1e3 * t_host),
-          file=sys.stderr, flush=True)
 
     xg = x.double().cpu().numpy()
-    ranks, flags = h.rank(), h.flags()
+    ranks, sflags = h.rank(), h.flags()
+    classes = h.classes()
     flops, byts = model(bt.ms, bt.rs, bt.ns)
-    achieved = byts / (push_ms / 1e3) / 1e9
-    tflops = flops / (push_ms / 1e3) / 1e12
     if args.copy_calibration > 0:
         n = args.copy_calibration * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device=dev)
@@ -267,23 +403,103 @@ def main():
             torch.neg(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
+
+    lds_gbs, lds_blocks, lds_iters = lds_peak(torch, rg, cus)
+    print("LDS read peak %.0f GB/s (%.1f B/clk/CU at 2.4 GHz)" % (lds_gbs, lds_gbs * 1e9 / cus / 2.4e9),
+          file=sys.stderr, flush=True)
     traffic = None if args.default_classes else measured_traffic(bt.B)
-    roof = {"bound": "mfma", "achieved": tflops, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-            "frac": tflops / PEAK_FP64_TFLOPS, "traffic": traffic,
-            "kernel": "k_push_mf (blocked dependent rows on FP64 matrix cores, m > 64 or r_max > 32) and "
-                      "k_push_rk (small streams), one launch per size class, concurrent; state on chip",
-            "algorithmic_flops_per_launch": flops, "algorithmic_state_bytes_per_launch": byts,
-            "state_bytes_rate_GBs": achieved, "launch_ms": push_ms}
+    per_class = None if args.no_classes else class_legs(torch, rg, bt, r_max, classes, stream, steps=3, warmup=1)
+    roof = {"bound": "lds", "peak": lds_gbs, "unit": "GB/s",
+            "peak_source": "LDS read probe of the library (rg_probe_lds_read), %d workgroups x %d iterations, "
+                           "best of 5, measured in this run" % (lds_blocks, lds_iters),
+            "traffic": traffic}
+    if per_class:
+        dom = max(per_class, key=lambda c: per_class[c]["launch_ms"])
+        pc = per_class[dom]
+        roof.update({"kernel": "k_push_mf variant %d (RMAX %s, MMAX %s, %d threads), its streams pushed alone"
+                               % (dom - 3, pc["r_max_cap"], pc["m_cap"], pc["threads"]) if dom >= 3 else
+                     "class %d" % dom,
+                     "achieved": pc["algorithmic_state_bytes"] / (pc["launch_ms"] * 1e-3) / 1e9,
+                     "launch_ms": pc["launch_ms"], "algorithmic_state_bytes_per_launch": pc["algorithmic_state_bytes"],
+                     "algorithmic_flops_per_launch": pc["algorithmic_flops"],
+                     "fp64_mfma_frac": pc["algorithmic_flops"] / (pc["launch_ms"] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS})
+        roof["frac"] = roof["achieved"] / lds_gbs
+    whole = {"launch_ms": push_ms, "algorithmic_state_bytes": byts, "algorithmic_flops": flops,
+             "state_bytes_rate_GBs": byts / (push_ms * 1e-3) / 1e9,
+             "lds_frac": byts / (push_ms * 1e-3) / 1e9 / lds_gbs,
+             "fp64_mfma_frac": flops / (push_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+             "note": "all classes concurrently, eager push (reset + push), HIP events"}
 
     out = {"metric": METRIC, "value": value, "unit": "row-updates/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "batched uneven streams: B=%d, m~U{16..256}, r~U{4..m/2}, n~U{m..8m}, "
                                   "FP32 state, FP64 rank test (eps 1e-3), rank capacity min(r+4, 128)" % bt.B,
-                      "streams": bt.B, "rows": rows,
+                      "streams": bt.B, "rows": rows, "launch": launch,
+                      "blocked_classes": "one workgroup per stream" if args.one_wg_per_stream else
+                                         "persistent grid per class, streams from a longest-first queue",
                       "class_placement": ("autotuned rules (%d)" % len(rules)) if rules else "default"},
-           "roofline": roof}
+           "roofline": roof,
+           "eager": {"ms_per_step": eager_ms, "push_ms": push_ms, "host_ms_per_step": 1e3 * t_host,
+                     "row_updates_per_s": rows / (eager_ms / 1e3)},
+           "push_all_classes": whole}
+    if per_class:
+        out["classes"] = {str(c): v for c, v in per_class.items()}
 
+    if not args.no_capacity:
+        # a capacity that does not know the planted rank: min(m, 128) for every stream
+        cap2 = np.minimum(bt.ms, 128).astype(np.int32)
+        with torch.cuda.stream(stream):
+            h2 = rg.Batch(bt.ms, r_max=cap2, dtype="f32", eps=1e-3, flags=flags, stream=stream)
+            h2.plan(bt.ns)
+            x2 = torch.empty(h2.n_x, dtype=torch.float32, device=dev)
+            p2, w2 = time_push(torch, h2, A, Y, rp, ao, x2, stream, max(3, args.steps // 2), 1)
+        r2, f2 = h2.rank(), h2.flags()
+        x2g = x2.double().cpu().numpy()
+        h2.close()
+        out["capacity_min_m_128"] = {"ms_per_step": w2, "push_ms": p2, "row_updates_per_s": rows / (w2 / 1e3),
+                                     "ranks_equal_planted": int((r2 == np.minimum(bt.rs, bt.ns)).sum()),
+                                     "flags_nonzero": int((f2 != 0).sum()),
+                                     "max_rel_diff_vs_headline_x": float(
+                                         np.max(np.abs(x2g - xg)) / max(np.max(np.abs(xg)), 1e-300)),
+                                     "launch": "eager"}
+        print("capacity min(m,128): %.3f ms/step" % w2, file=sys.stderr, flush=True)
+
+    if not args.no_single:
+        gold = os.path.join(ROOT, "tests", "golden")
+
+        def _gold(name):
+            path = os.path.join(gold, name)
+            if not os.path.exists(path):
+                return None
+            with np.load(path, allow_pickle=False) as z:
+                return z["x"], int(z["rank"])
+        singles = {}
+        s0 = W.single_f64()
+        from oracle import ref_c
+        ref_c.build()
+        xo0, ro0, *_ = ref_c.solve(s0.A, s0.Y, eps=s0.eps)
+        singles["small_f64"] = single_leg(torch, rg, "m=64, r=16, n=2000, FP64, eps 1e-10", s0, "f64",
+                                          golden=(xo0, ro0), steps=3)
+        for dt in ("f64", "f32"):
+            s1 = W.large_stream(dtype=dt)
+            singles["large_" + dt] = single_leg(
+                torch, rg, "m=2048, r=256, n=20000 (10%% copies, 5%% combinations), %s" % dt.upper(), s1, dt,
+                golden=_gold("large_stream_%s.npz" % dt))
+            del s1
+        s3 = W.stress()
+        g3 = None
+        path = os.path.join(gold, "stress_f32.npz")
+        if os.path.exists(path):
+            with np.load(path, allow_pickle=False) as z:
+                g3 = (z["x"][-1], int(z["rank"][-1]))
+        singles["stress_f32"] = single_leg(torch, rg, "m=1024, r=128, n=50000, spectrum 1..1e-6, FP32", s3, "f32",
+                                           golden=g3)
+        out["single_streams"] = singles
+        print("single streams: " + ", ".join("%s %.2f us/row" % (k, v["us_per_row"]) for k, v in singles.items()),
+              file=sys.stderr, flush=True)
+
+    h.close()
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg(torch, rg, W, steps=5, warmup=1)
         print("adjoint leg: forward %.3f ms, backward %.3f ms" % (out["adjoint"]["forward_ms"],
@@ -318,7 +534,7 @@ def main():
             kap[b] = np.linalg.cond(Ab[:int(ro[b])].astype(np.float64)) if ro[b] > 0 else 1.0
         good = kap <= 1e3
         out["error"] = {"rank_match": int((ranks == ro).sum()), "streams": bt.B,
-                        "flags_nonzero": int((flags != 0).sum()),
+                        "flags_nonzero": int((sflags != 0).sum()),
                         "rel_err_max": float(errs.max()), "rel_err_median": float(np.median(errs)),
                         "rel_err_p99": float(np.percentile(errs, 99)),
                         "rel_err_max_kappa_le_1e3": float(errs[good].max()) if good.any() else None,

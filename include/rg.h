@@ -84,6 +84,10 @@ typedef enum { RG_F32 = 0, RG_F64 = 1 } rg_dtype;
                                        orthonormal rows and C-tilde = C.  Streams with either
                                        variant bit run in the global-memory kernel; setting
                                        both bits is RG_E_INVALID */
+#define RG_OPT_ONE_WG_PER_STREAM 0x80u  /* blocked on-chip classes: one workgroup per stream
+                                          instead of the persistent grid (as many workgroups
+                                          as fit on the chip, each taking streams from a
+                                          queue, longest expected cost first) */
 
 typedef struct {
     int32_t dtype;   /* rg_dtype */
@@ -193,6 +197,10 @@ rg_status rg_batch_rank(rg_handle h, int32_t *r);
 /* Flags (host, B uint32).  Synchronises. */
 rg_status rg_batch_flags(rg_handle h, uint32_t *flags);
 
+/* Kernel class of every stream (host, B int32): 0 .. rg_class_count()-1, or
+ * -1 for the global-memory kernel.  Fixed at init; does not synchronise. */
+rg_status rg_batch_classes(rg_handle h, int32_t *cls);
+
 /* Copy stream b's state to caller buffers (device; any may be NULL): C and
  * Ct as r x m row-major in the handle dtype, Pinv as r x r row-major doubles,
  * w as r doubles,
@@ -297,6 +305,16 @@ rg_status rg_class_fits(int32_t cls, int32_t m, int32_t r_max, int32_t *fits);
  * The arrays (host, n entries) are copied; n = 0 restores the default.  Not
  * safe to call while another thread creates a handle. */
 rg_status rg_set_class_rules(const int32_t *m_hi, const int32_t *r_max_hi, const int32_t *cls, int32_t n);
+
+/* ---- measurement ------------------------------------------------------- */
+
+/* LDS read-bandwidth probe, the reference for the on-chip kernels' state
+ * traffic: launches blocks workgroups of 256 threads on stream (hipStream_t,
+ * NULL = default); each thread reads 128 bytes of LDS per iteration for iters
+ * iterations, so one launch reads blocks * 256 * 128 * iters bytes.  out
+ * (device, blocks * 256 floats) receives a value that depends on the reads.
+ * Stream-ordered; time it with events around the call. */
+rg_status rg_probe_lds_read(void *out, int32_t blocks, int32_t iters, void *stream);
 
 /* Device bytes the workspace of such a batch takes. */
 size_t rg_workspace_bytes(int32_t B, const int32_t *m, const int32_t *r_max, int32_t dtype);

@@ -8,7 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librg.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["rg_api.hip", "rg_generic.hip", "rg_rk.hip", "rg_mf.hip", "rg_big.hip", "rg_pinv_track.hip"]
+SOURCES = ["rg_api.hip", "rg_generic.hip", "rg_rk.hip", "rg_mf.hip", "rg_big.hip", "rg_pinv_track.hip",
+           "rg_probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -169,6 +169,7 @@ rg_status push_impl(rg_ctx *h, const void *gamma, const void *y, const int64_t *
     a.k_single = k_single;
     a.eps = h->eps;
     a.opts = h->opts;
+    a.persistent = (h->opts & RG_OPT_ONE_WG_PER_STREAM) ? 0 : 1;
     HIPCHK(rg::launch_reset_counter(h->d_counter, h->stream));
     // Size-class families run concurrently on forked streams (largest class
     // first), joined back into the handle's stream.
@@ -501,6 +502,18 @@ rg_status rg_batch_flags(rg_handle h, uint32_t *flags) {
     if (st != RG_OK) return st;
     for (int b = 0; b < h->B; ++b) flags[b] = M[b].flags;
     return RG_OK;
+}
+
+rg_status rg_batch_classes(rg_handle h, int32_t *cls) {
+    if (!valid_handle(h) || !cls) return RG_E_INVALID;
+    for (int b = 0; b < h->B; ++b) cls[b] = h->h_meta[b].cls;
+    return RG_OK;
+}
+
+rg_status rg_probe_lds_read(void *out, int32_t blocks, int32_t iters, void *stream) {
+    if (!out || blocks < 1 || iters < 1) return RG_E_INVALID;
+    return rg::launch_lds_probe((float *)out, blocks, iters, (hipStream_t)stream) == hipSuccess ? RG_OK
+                                                                                                 : RG_E_DEVICE;
 }
 
 rg_status rg_rank(rg_handle h, int32_t *r) {

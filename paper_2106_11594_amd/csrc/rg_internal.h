@@ -31,6 +31,7 @@ constexpr uint32_t OPT_ROW_BY_ROW = 0x8u;
 constexpr uint32_t OPT_DEPENDENT_BLOCKS_ONLY = 0x10u;
 constexpr uint32_t OPT_ORTHOGONAL = 0x20u;
 constexpr uint32_t OPT_ORTHONORMAL = 0x40u;
+constexpr uint32_t OPT_ONE_WG_PER_STREAM = 0x80u;
 
 // Arguments of a push launch (by value).
 template <typename T>
@@ -50,12 +51,18 @@ struct PushArgs {
     int64_t k_single;
     double eps;              // < 0: default of Section 3 at the current rank
     uint32_t opts;
+    int32_t persistent;      // on-chip classes: persistent grid taking streams from the queue head
 };
 
 // Host-side launchers (defined in the kernel sources).
 template <typename T>
 hipError_t launch_push_generic(const PushArgs<T> &a, int grid, int m_max, int r_max_max, hipStream_t s);
 hipError_t launch_reset_counter(uint32_t *counter, hipStream_t s);
+// LDS read-bandwidth probe (rg_probe.hip): blocks x 256 threads, each thread
+// reads LDS_PROBE_BYTES_PER_THREAD_ITER bytes per iteration.
+constexpr int LDS_PROBE_THREADS = 256;
+constexpr int LDS_PROBE_BYTES_PER_THREAD_ITER = 8 * 16;
+hipError_t launch_lds_probe(float *out, int blocks, int iters, hipStream_t s);
 hipError_t launch_reset_streams(StreamMeta *meta, int B, hipStream_t s);
 // One large stream over the whole GPU (rg_big.hip): streams of single-stream
 // handles with m >= BIG_M_MIN that no on-chip class holds.

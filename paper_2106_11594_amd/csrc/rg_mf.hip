@@ -54,6 +54,8 @@
 //   C <- [C; Gamma_blk], P^-1 <- diag(P^-1, I), w <- [w; y_blk].
 //   The first row of the other kind ends the block.
 // Every branch is on workgroup-uniform values.
+#include <algorithm>
+
 #include "rg_classes.h"
 #include "rg_lanes.h"
 
@@ -146,11 +148,12 @@ __device__ inline void block_sum4(double &a, double &b, double &c, double &d, do
     }
 }
 
+// One stream's push by the whole workgroup (every thread calls it with the same
+// b_id and returns at the same point).
 template <class K>
-__global__ void __launch_bounds__(K::NT, K::OCC) k_push_mf(PushArgs<float> a, int ra) {
+__device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, int b_id, double *smem) {
     constexpr int RMAX = K::RMAX, MMAX = K::MMAX, NU = K::NU, UPW = K::UPW, TPW = K::TPW;
     constexpr int NB = K::NB, KB = K::KB, CH = K::CH, NW = K::NW, NTT = K::NTT, RS = K::RS;
-    extern __shared__ double smem[];
     float *sct = reinterpret_cast<float *>(smem);  // C: ra x MMAX (ra: multiple of 16)
     double *x1 = smem + (size_t)ra * MMAX / 2;
     double *x2 = x1 + K::X1_D;
@@ -158,7 +161,6 @@ __global__ void __launch_bounds__(K::NT, K::OCC) k_push_mf(PushArgs<float> a, in
     float *ring = reinterpret_cast<float *>(x2);  // row mode: 3 rows of MMAX
 
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    const int b_id = a.order[blockIdx.x];
     StreamMeta *M = a.meta + b_id;
     const int m = M->m, rmax = M->r_max, ldm = M->ldm;
     int r = M->r;
@@ -1188,6 +1190,30 @@ __global__ void __launch_bounds__(K::NT, K::OCC) k_push_mf(PushArgs<float> a, in
     __syncthreads();
 }
 
+// Grid of one workgroup per stream (a.persistent == 0), or a persistent grid
+// whose workgroups take streams from the family's queue head, in the order of
+// a.order (longest expected cost first), until the queue is empty.  The queue
+// head is read by thread 0 and handed to the workgroup through LDS; the
+// barrier after the last stream's stores keeps that read and the previous
+// stream's thread-0 stores in separate barrier intervals.
+template <class K>
+__global__ void __launch_bounds__(K::NT, K::OCC) k_push_mf(PushArgs<float> a, int ra) {
+    extern __shared__ double smem[];
+    if (!a.persistent) {
+        push_stream<K>(a, ra, a.order[blockIdx.x], smem);
+        return;
+    }
+    int *slot = reinterpret_cast<int *>(smem + (size_t)ra * K::MMAX / 2);  // first word of X1
+    for (;;) {
+        if (threadIdx.x == 0) *slot = (int)atomicAdd(a.counter, 1u);
+        __syncthreads();
+        const int q = *slot;
+        __syncthreads();
+        if (q >= a.n_order) break;
+        push_stream<K>(a, ra, a.order[q], smem);
+    }
+}
+
 template <class K>
 size_t lds_bytes(int ra) {
     return sizeof(float) * (size_t)ra * K::MMAX + sizeof(double) * (size_t)(K::X1_D + K::X2_D);
@@ -1210,22 +1236,51 @@ bool fits_k(int m, int r_max) {
 // Set once per variant, to the LDS the variant needs at its full rank
 // capacity (the limit is process-wide: a later handle must not lower it under
 // the launches of a live one).
+// Workgroups of variant K resident on the chip at once for a given LDS need
+// (the persistent grid), looked up when a handle is set up, never during a
+// push, so that a push can be captured into a graph.
+template <class K>
+struct Resident {
+    static int per_ra[K::RMAX / 16 + 1];  // by rows16(r_max) / 16; 0 = not looked up
+    static int cus;
+};
+template <class K>
+int Resident<K>::per_ra[K::RMAX / 16 + 1] = {};
+template <class K>
+int Resident<K>::cus = 0;
+
 template <class K>
 hipError_t prepare_k(int r_max) {
-    if (lds_bytes<K>(rows16(r_max)) > 160 * 1024) return hipErrorInvalidValue;
+    const int ra = rows16(r_max);
+    if (lds_bytes<K>(ra) > 160 * 1024) return hipErrorInvalidValue;
     static_assert(sizeof(float) * K::RMAX * K::MMAX + sizeof(double) * (K::X1_D + K::X2_D) <= 160 * 1024,
                   "every variant fits the LDS at its full capacity");
     static const hipError_t once = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_push_mf<K>),
                                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                                        (int)lds_bytes<K>(K::RMAX));
-    return once;
+    if (once != hipSuccess) return once;
+    int per_cu = 0, dev = 0, cus = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_push_mf<K>, K::NT, lds_bytes<K>(ra));
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    Resident<K>::per_ra[ra / 16] = per_cu > 0 ? per_cu : 1;
+    Resident<K>::cus = cus;
+    return hipSuccess;
 }
 template <class K>
 hipError_t launch_k(const PushArgs<float> &a, int r_max, hipStream_t s) {
     const int ra = rows16(r_max);
     const size_t lds = lds_bytes<K>(ra);
     if (lds > 160 * 1024 || ra > K::RMAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_push_mf<K>, dim3(a.n_order), dim3(K::NT), lds, s, a, ra);
+    int grid = a.n_order;
+    if (a.persistent) {
+        // as many workgroups as fit on the chip at once, each taking streams from the queue
+        const int per_cu = Resident<K>::per_ra[ra / 16];
+        if (per_cu <= 0 || Resident<K>::cus <= 0) return hipErrorNotInitialized;
+        grid = std::max(1, std::min(a.n_order, per_cu * Resident<K>::cus));
+    }
+    hipLaunchKernelGGL(k_push_mf<K>, dim3(grid), dim3(K::NT), lds, s, a, ra);
     return hipGetLastError();
 }
 

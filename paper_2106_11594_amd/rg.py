@@ -20,6 +20,7 @@ FLAG_NONFINITE, FLAG_RANK_CAPACITY, FLAG_DENOMINATOR = 0x1, 0x2, 0x4
 OPT_NO_REPROJECT, OPT_GENERIC_KERNEL, OPT_SERIAL_CLASSES, OPT_ROW_BY_ROW = 0x1, 0x2, 0x4, 0x8
 OPT_DEPENDENT_BLOCKS_ONLY = 0x10
 OPT_ORTHOGONAL, OPT_ORTHONORMAL = 0x20, 0x40
+OPT_ONE_WG_PER_STREAM = 0x80
 OK, E_INVALID, E_NOMEM, E_DEVICE, E_RANK_CAPACITY, E_NONFINITE, E_STATE, E_UNSUPPORTED = range(8)
 _STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "HIP runtime error", 4: "rank capacity reached",
            5: "non-finite row or target", 6: "stream is flagged", 7: "unsupported size"}
@@ -53,6 +54,8 @@ _SIGS = {
     "rg_batch_init_ws": (ctypes.c_int, [_p, _i32, _p, _p, _p, _p, ctypes.c_size_t]),
     "rg_batch_check_layout": (ctypes.c_int, [_p, _p, _p, _i64, _i64]),
     "rg_batch_status": (ctypes.c_int, [_p, _p]),
+    "rg_batch_classes": (ctypes.c_int, [_p, _p]),
+    "rg_probe_lds_read": (ctypes.c_int, [_p, _i32, _i32, _p]),
     "rg_destroy": (ctypes.c_int, [_p]),
     "rg_batch_init": (ctypes.c_int, [_p, _i32, _p, _p, _p]),
     "rg_batch_push": (ctypes.c_int, [_p, _p, _p, _p, _p]),
@@ -204,6 +207,12 @@ class Batch:
         f = np.zeros(self.B, dtype=np.uint32)
         _check(lib().rg_batch_flags(self._h, f.ctypes.data_as(_p)), "rg_batch_flags")
         return f
+
+    def classes(self):
+        """Kernel class of every stream (rg_batch_classes; -1 = generic kernel)."""
+        c = np.zeros(self.B, dtype=np.int32)
+        _check(lib().rg_batch_classes(self._h, c.ctypes.data_as(_p)), "rg_batch_classes")
+        return c
 
     def status(self):
         """Per-stream status codes (rg_batch_status): OK, E_NONFINITE,
@@ -509,3 +518,18 @@ def set_class_rules(rules):
     c = np.array([r[2] for r in rules] or [0], dtype=np.int32)
     _check(lib().rg_set_class_rules(a.ctypes.data_as(ctypes.c_void_p), b.ctypes.data_as(ctypes.c_void_p),
                                     c.ctypes.data_as(ctypes.c_void_p), len(rules)), "rg_set_class_rules")
+
+
+LDS_PROBE_BYTES_PER_THREAD_ITER = 128
+LDS_PROBE_THREADS = 256
+
+
+def probe_lds_read(out, blocks, iters, stream=None):
+    """rg_probe_lds_read: enqueue the LDS read-bandwidth probe; out is a CUDA
+    float32 tensor of blocks * 256 elements.  Returns the bytes it reads."""
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    _check(lib().rg_probe_lds_read(_dev(out, torch.float32, "out", blocks * LDS_PROBE_THREADS), int(blocks),
+                                   int(iters), ctypes.c_void_p(stream.cuda_stream)), "rg_probe_lds_read")
+    return blocks * LDS_PROBE_THREADS * LDS_PROBE_BYTES_PER_THREAD_ITER * iters

@@ -217,3 +217,20 @@ def test_rank_fills_the_capacity_exactly(m, cap):
     tol, _ = _kappa_tol(Co)
     assert f == 0 and r == ro == cap
     assert _rel(x, xo) <= tol
+
+
+@pytest.mark.gpu
+def test_persistent_grid_equals_one_workgroup_per_stream():
+    """The persistent grid (workgroups taking streams from a queue) and one
+    workgroup per stream run the same per-stream arithmetic: bit-equal x,
+    equal ranks and flags, on a batch that covers every blocked variant."""
+    from paper_2106_11594_amd import rg
+    from tests.gpu_util import run_batch
+    bt = W.batched(B=160, n_scale=0.3, dtype="f32", seed=11)
+    caps = np.minimum(bt.ms, np.minimum(bt.rs + 4, 128)).astype(np.int32)
+    xa, ra, fa, ha = run_batch(bt, "f32", r_max=caps, eps=1e-3)
+    xb, rb, fb, hb = run_batch(bt, "f32", r_max=caps, eps=1e-3, flags=rg.OPT_ONE_WG_PER_STREAM)
+    assert len(set(ha.classes()) & {3, 4, 5, 6, 7, 8}) >= 4
+    assert (ra == rb).all() and (fa == fb).all() and (fa == 0).all()
+    for b in range(bt.B):
+        assert np.array_equal(xa[b], xb[b]), b
