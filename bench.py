@@ -153,12 +153,13 @@ def adjoint_leg(torch, rg, W, steps, warmup):
                                   "algorithmic_bytes": bytes_bw}}
 
 
-def pinv_track_leg(torch, rg, W, steps, warmup, B=256, n=256, m=64, r=16):
+def pinv_track_leg(torch, rg, W, steps, warmup, B=1024, n=256, m=64, r=16):
     """Theorems 2 and 3 (A^+ maintained row by row), FP64: B problems of n rows
-    of m regressors at planted rank r, one workgroup each, timed with HIP
-    events on the current stream.  Algorithmic bytes per row i: the A^+ update
-    reads and writes m (i+1) values, beta reads i r_i values of B, the two
-    projections read r_i m values of C and of Ct, plus the row itself."""
+    of m regressors at planted rank r, one workgroup each (B = 1024: four per
+    CU, so that one problem's latency hides behind the others'), timed with
+    HIP events on the current stream.  Algorithmic bytes per row i: the A^+
+    update reads and writes m (i+1) values, beta reads i r_i values of B, the
+    two projections read r_i m values of C and of Ct, plus the row itself."""
     rng = np.random.default_rng(5)
     A = np.stack([W.lowrank_rows(rng, m, r, n) for _ in range(B)]).astype(np.float64)
     Y = np.stack([W.targets(rng, A[b])[0] for b in range(B)]).astype(np.float64)

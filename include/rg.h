@@ -262,6 +262,17 @@ rg_status rg_pinv_track(const double *A, const double *Y, int32_t B, int32_t n, 
                         double eps, double *Ap, double *X, int32_t *rank, uint32_t *flags, void *work,
                         size_t work_bytes, void *stream);
 
+/* rg_pinv_track with q >= 1 right-hand sides: Y (device, B x n x q; row i of
+ * problem b has the q targets Y[(b n + i) q + c]) and X (device output,
+ * B x m x q, the minimum-norm least-squares solutions X = A^+ Y, row-major).
+ * Every right-hand side takes the same gain K per row, X <- X + K (y_i^T -
+ * Gamma^T X); with Y = I_n, X equals A^+.  A non-finite target in any column
+ * sets RG_FLAG_NONFINITE.  The LDS need grows by q doubles (RG_E_UNSUPPORTED
+ * past 160 KiB); otherwise as rg_pinv_track, which is this call with q = 1. */
+rg_status rg_pinv_track_rhs(const double *A, const double *Y, int32_t B, int32_t n, int32_t m, int32_t q,
+                            int32_t r_max, double eps, double *Ap, double *X, int32_t *rank, uint32_t *flags,
+                            void *work, size_t work_bytes, void *stream);
+
 /* rg_pinv_track for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
  * the same computation and outputs, with the workspace taken from a fixed

@@ -31,7 +31,7 @@ import math
 __all__ = [
     "RGState", "default_eps", "is_dependent", "update_least_squares",
     "solve_stream", "lstsq_exact", "rref_row_basis", "pinv_from_state",
-    "lstsq_svd", "penrose_residuals",
+    "lstsq_svd", "penrose_residuals", "stability_factor", "residual_error",
 ]
 
 
@@ -314,3 +314,30 @@ def penrose_residuals(A, Ap):
     r3 = AAp.T - AAp
     r4 = ApA.T - ApA
     return [abs(np.asarray(r)).max() if r.size else 0 for r in (r1, r2, r3, r4)]
+
+
+# --------------------------------------------------------------------------
+# Stability measures of Section 4.2 (numpy, FP64).
+# --------------------------------------------------------------------------
+
+def stability_factor(Ap_algo, Ap_exact, A, eps_machine=2.0 ** -52):
+    """Stability factor of a computed pseudoinverse (Section 4.2, first
+    measure): ||Ap_algo - A^+||_2 / (eps_M ||A^+||_2 kappa_2(A)), with the
+    2-norm the largest singular value and kappa_2 = s_max / s_min of A."""
+    import numpy as np
+    A = np.asarray(A, dtype=np.float64)
+    s = np.linalg.svd(A, compute_uv=False)
+    kappa = s[0] / s[-1]
+    num = np.linalg.norm(np.asarray(Ap_algo, np.float64) - np.asarray(Ap_exact, np.float64), 2)
+    return num / (eps_machine * np.linalg.norm(np.asarray(Ap_exact, np.float64), 2) * kappa)
+
+
+def residual_error(Ap_algo, A):
+    """Residual error of a computed pseudoinverse (Section 4.2, second
+    measure): ||Ap_algo A - I||_2 / (||A||_2 ||Ap_algo||_2), I the identity
+    of the size of Ap_algo A."""
+    import numpy as np
+    A = np.asarray(A, dtype=np.float64)
+    Ap = np.asarray(Ap_algo, dtype=np.float64)
+    R = Ap @ A - np.eye(A.shape[1])
+    return np.linalg.norm(R, 2) / (np.linalg.norm(A, 2) * np.linalg.norm(Ap, 2))

@@ -210,7 +210,8 @@ rg_status push_impl(rg_ctx *h, const void *gamma, const void *y, const int64_t *
         a.order = h->d_order + h->fam_begin[0];
         a.n_order = h->fam_count[0];
         a.counter = h->d_counter;
-        const size_t lds = sizeof(double) * (2 * (size_t)h->m_max_generic + 3 * (size_t)h->rmax_max_generic + 8);
+        const size_t lds = rg::generic_lds_bytes<T>(
+            h->m_max_generic, h->rmax_max_generic, rg::generic_state_in_lds<T>(h->m_max_generic, h->rmax_max_generic));
         int per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / lds));
         int grid = std::min(h->fam_count[0], h->num_cus * per_cu);
         HIPCHK(rg::launch_push_generic<T>(a, grid, h->m_max_generic, h->rmax_max_generic, h->stream));

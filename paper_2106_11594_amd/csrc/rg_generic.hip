@@ -29,11 +29,9 @@ constexpr int NW = NT / 64;
 // conditioned bases (measured against the FP64 oracle).
 template <typename T> struct AccG { using type = double; };
 
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
+// Sum over the 64 lanes of a wave with DPP and permlane steps (no LDS round
+// trips); every lane gets the same bits.
+__device__ inline double wave_sum(double v) { return sum64(v); }
 
 // Sum a and b over the workgroup; every thread gets the totals.  Fixed
 // order, so the result does not depend on scheduling.
@@ -84,17 +82,46 @@ __device__ inline double reject(const T *C, int ldm, const double *v, const doub
     return s;
 }
 
+// Bytes of one stream's state held in LDS (C and Ct, rmax x ldm each, then
+// P^-1 and w in doubles).
+template <typename T>
+__host__ __device__ inline size_t lds_state_bytes(int rmax, int ldm) {
+    const size_t ct = 2 * (size_t)rmax * ldm * sizeof(T);
+    return (ct + 7) / 8 * 8 + sizeof(double) * ((size_t)rmax * rmax + rmax);
+}
+
 template <typename T>
 __device__ void run_stream(const PushArgs<T> &a, int b, double *sG, double *sGr, double *sGam, double *sGam2,
-                           double *sZ, double *sRed) {
+                           double *sZ, double *sRed, double *sState) {
     StreamMeta *M = a.meta + b;
     const int m = M->m, rmax = M->r_max, ldm = M->ldm;
     int r = M->r;
     uint32_t flags = M->flags;
-    T *C = a.state + M->state_off;
+    T *const Cg = a.state + M->state_off;
+    double *const Pg = a.preg + M->p_off;
+    double *const wg = a.wreg + M->w_off;
+    T *C = Cg;
     T *Ct = C + (size_t)rmax * ldm;
-    double *P = a.preg + M->p_off;
-    double *w = a.wreg + M->w_off;
+    double *P = Pg;
+    double *w = wg;
+    // With sState (the launch reserved room for the largest stream), the push
+    // works on an LDS copy of the state: loaded here, written back at the end.
+    if (sState) {
+        C = reinterpret_cast<T *>(sState);
+        Ct = C + (size_t)rmax * ldm;
+        P = sState + (2 * (size_t)rmax * ldm * sizeof(T) + 7) / 8;
+        w = P + (size_t)rmax * rmax;
+        for (int idx = threadIdx.x; idx < r * ldm; idx += NT) {
+            C[idx] = Cg[idx];
+            Ct[idx] = Cg[(size_t)rmax * ldm + idx];
+        }
+        for (int idx = threadIdx.x; idx < r * r; idx += NT) {
+            const int ii = idx / r, k = idx - ii * r;
+            P[(size_t)ii * rmax + k] = Pg[(size_t)ii * rmax + k];
+        }
+        for (int k = threadIdx.x; k < r; k += NT) w[k] = wg[k];
+        __syncthreads();
+    }
     int64_t i0, i1, goff;
     if (a.row_ptr) {
         i0 = a.row_ptr[b];
@@ -245,6 +272,17 @@ __device__ void run_stream(const PushArgs<T> &a, int b, double *sG, double *sGr,
         __syncthreads();
     }
     __syncthreads();
+    if (sState) {
+        for (int idx = tid; idx < r * ldm; idx += NT) {
+            Cg[idx] = C[idx];
+            Cg[(size_t)rmax * ldm + idx] = Ct[idx];
+        }
+        for (int idx = tid; idx < r * r; idx += NT) {
+            const int ii = idx / r, k = idx - ii * r;
+            Pg[(size_t)ii * rmax + k] = P[(size_t)ii * rmax + k];
+        }
+        for (int k = tid; k < r; k += NT) wg[k] = w[k];
+    }
     if (tid == 0) {
         M->r = r;
         M->flags = flags;
@@ -259,7 +297,7 @@ __device__ void run_stream(const PushArgs<T> &a, int b, double *sG, double *sGr,
 }
 
 template <typename T>
-__global__ void __launch_bounds__(NT) k_push_generic(PushArgs<T> a, int m_max, int r_max_max) {
+__global__ void __launch_bounds__(NT) k_push_generic(PushArgs<T> a, int m_max, int r_max_max, int lds_state) {
     extern __shared__ double smem[];
     double *sG = smem;
     double *sGr = sG + m_max;
@@ -267,6 +305,7 @@ __global__ void __launch_bounds__(NT) k_push_generic(PushArgs<T> a, int m_max, i
     double *sGam2 = sGam + r_max_max;
     double *sZ = sGam2 + r_max_max;
     double *sRed = sZ + r_max_max;
+    double *sState = lds_state ? sRed + 2 * NW : nullptr;
     __shared__ int s_idx;
     for (;;) {
         if (threadIdx.x == 0) s_idx = (int)atomicAdd(a.counter, 1u);
@@ -275,7 +314,7 @@ __global__ void __launch_bounds__(NT) k_push_generic(PushArgs<T> a, int m_max, i
         __syncthreads();
         if (idx >= a.n_order) break;
         const int b = a.order[idx];
-        if (a.meta[b].cls < 0) run_stream<T>(a, b, sG, sGr, sGam, sGam2, sZ, sRed);
+        if (a.meta[b].cls < 0) run_stream<T>(a, b, sG, sGr, sGam, sGam2, sZ, sRed, sState);
     }
 }
 
@@ -532,12 +571,29 @@ template hipError_t launch_ctilde<double>(const StreamMeta *, int, const double 
                                           hipStream_t);
 
 template <typename T>
+size_t generic_lds_bytes(int m_max, int r_max_max, bool lds_state) {
+    const size_t base = sizeof(double) * (2 * (size_t)m_max + 3 * (size_t)r_max_max + 2 * NW);
+    const int ldm_max = (int)((m_max + 16 / sizeof(T) - 1) / (16 / sizeof(T)) * (16 / sizeof(T)));
+    return base + (lds_state ? lds_state_bytes<T>(r_max_max, ldm_max) : 0);
+}
+
+template <typename T>
+bool generic_state_in_lds(int m_max, int r_max_max) {
+    return generic_lds_bytes<T>(m_max, r_max_max, true) <= 64 * 1024;
+}
+
+template <typename T>
 hipError_t launch_push_generic(const PushArgs<T> &a, int grid, int m_max, int r_max_max, hipStream_t s) {
-    const size_t lds = sizeof(double) * (2 * (size_t)m_max + 3 * (size_t)r_max_max + 2 * NW);
+    const bool in_lds = generic_state_in_lds<T>(m_max, r_max_max);
+    const size_t lds = generic_lds_bytes<T>(m_max, r_max_max, in_lds);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_push_generic<T>, dim3(grid), dim3(NT), lds, s, a, m_max, r_max_max);
+    hipLaunchKernelGGL(k_push_generic<T>, dim3(grid), dim3(NT), lds, s, a, m_max, r_max_max, in_lds ? 1 : 0);
     return hipGetLastError();
 }
+template size_t generic_lds_bytes<float>(int, int, bool);
+template size_t generic_lds_bytes<double>(int, int, bool);
+template bool generic_state_in_lds<float>(int, int);
+template bool generic_state_in_lds<double>(int, int);
 
 hipError_t launch_reset_counter(uint32_t *counter, hipStream_t s) {
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, counter);

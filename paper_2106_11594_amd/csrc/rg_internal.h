@@ -57,6 +57,12 @@ struct PushArgs {
 // Host-side launchers (defined in the kernel sources).
 template <typename T>
 hipError_t launch_push_generic(const PushArgs<T> &a, int grid, int m_max, int r_max_max, hipStream_t s);
+// Dynamic LDS of the generic kernel, and whether it keeps each stream's state
+// in LDS during a push (when that fits in 64 KiB per workgroup).
+template <typename T>
+size_t generic_lds_bytes(int m_max, int r_max_max, bool lds_state);
+template <typename T>
+bool generic_state_in_lds(int m_max, int r_max_max);
 hipError_t launch_reset_counter(uint32_t *counter, hipStream_t s);
 // LDS read-bandwidth probe (rg_probe.hip): blocks x 256 threads, each thread
 // reads LDS_PROBE_BYTES_PER_THREAD_ITER bytes per iteration.

@@ -13,14 +13,17 @@
 //   Ct -= gamma K^T), borders P^-1 with 1 and B with the unit coordinate
 //   e_{r+1}; dependent downdates P^-1 by zeta zeta^T / (1 + gamma^T zeta) and
 //   appends gamma to B.
-// B (n x r_max) is the coordinate factor of A = B C; it is needed only for
-// beta, which is what makes the pseudoinverse update O(m n) per row.
+// B (n x r_max, stored transposed) is the coordinate factor of A = B C; it
+// is needed only for beta, which is what makes the pseudoinverse update
+// O(m n) per row.  beta lives in LDS when it fits.
 //
 // The A^+ update reads and writes m x (i+1) values per row i, so the kernel is
 // bound by memory traffic to the L2 / HBM, not by arithmetic: per row it moves
 // about 16 m (i+1) bytes of A^+ plus 8 (i + 3 m r) bytes of B, C and Ct.
 #include "../../include/rg.h"
 #include <hip/hip_runtime.h>
+
+#include "rg_lanes.h"
 #include <cfloat>
 #include <cmath>
 #include <mutex>
@@ -30,11 +33,9 @@ namespace {
 constexpr int NT = 256;
 constexpr int NW = NT / 64;
 
-__device__ inline double wsum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
+// Sum over the 64 lanes of a wave (DPP and permlane steps, the same bits on
+// every lane).
+__device__ inline double wsum(double v) { return rg::sum64(v); }
 
 // Sum a, b and c over the workgroup in a fixed order; every thread gets the
 // same totals, so decisions taken on them are uniform.
@@ -63,45 +64,55 @@ inline size_t per_problem(int n, int m, int rmax) {
     return 2 * (size_t)rmax * m + (size_t)rmax * rmax + (size_t)n * rmax + (size_t)n;
 }
 
-__global__ void __launch_bounds__(NT) k_pinv_track(const double *A, const double *Y, int n, int m, int rmax,
+__global__ void __launch_bounds__(NT) k_pinv_track(const double *A, const double *Y, int n, int m, int q, int rmax,
                                                    double eps_in, double *Ap, double *X, int32_t *rank,
-                                                   uint32_t *flags, double *work, size_t per) {
+                                                   uint32_t *flags, double *work, size_t per, bool beta_lds) {
     extern __shared__ double sm[];
-    double *sG = sm, *sR = sG + m, *sK = sR + m, *sg = sK + m, *sz = sg + rmax, *red = sz + rmax;
+    double *sG = sm, *sR = sG + m, *sK = sR + m, *sg = sK + m, *sz = sg + rmax, *sdy = sz + rmax, *red = sdy + q;
     const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     double *C = work + (size_t)b * per;
     double *Ct = C + (size_t)rmax * m;
     double *P = Ct + (size_t)rmax * m;
-    double *Bf = P + (size_t)rmax * rmax;
-    double *beta = Bf + (size_t)n * rmax;
+    double *Bf = P + (size_t)rmax * rmax;  // B^T: column t of B (row t of A's coordinates) at stride n
+    // beta in LDS after the other vectors when it fits there, else in the workspace
+    double *beta = beta_lds ? red + 3 * NW : Bf + (size_t)n * rmax;
     const double *Ab = A + (size_t)b * n * m;
-    const double *Yb = Y + (size_t)b * n;
+    const double *Yb = Y + (size_t)b * n * q;
     double *Apb = Ap + (size_t)b * m * n;
-    double *Xb = X + (size_t)b * m;
+    double *Xb = X + (size_t)b * m * q;
 
     // Zero P^-1 and B: bordering then only writes the new diagonal / unit entry.
     for (size_t t = tid; t < (size_t)rmax * rmax; t += NT) P[t] = 0.0;
     for (size_t t = tid; t < (size_t)n * rmax; t += NT) Bf[t] = 0.0;
-    for (int j = tid; j < m; j += NT) Xb[j] = 0.0;
+    for (int j = tid; j < m * q; j += NT) Xb[j] = 0.0;
     __syncthreads();
 
     int r = 0;
     uint32_t fl = 0;
     for (int i = 0; i < n; ++i) {
         const double *G = Ab + (size_t)i * m;
-        const double y = Yb[i];
+        const double *yi = Yb + (size_t)i * q;
         for (int j = tid; j < m; j += NT) sG[j] = G[j];
         __syncthreads();
-        // gamma = Ct Gamma: one wave per row k of Ct, lanes over j.
-        for (int k = wid; k < r; k += NW) {
+        // gamma = Ct Gamma (tasks k < r) and the a priori residuals
+        // dy_c = y_c - Gamma^T X[:, c] (tasks r + c): one wave per task, lanes over j.
+        for (int task = wid; task < r + q; task += NW) {
             double acc = 0.0;
-            for (int j = lane; j < m; j += 64) acc += Ct[(size_t)k * m + j] * sG[j];
+            if (task < r) {
+                for (int j = lane; j < m; j += 64) acc += Ct[(size_t)task * m + j] * sG[j];
+            } else {
+                const int c = task - r;
+                for (int j = lane; j < m; j += 64) acc += sG[j] * Xb[(size_t)j * q + c];
+            }
             acc = wsum(acc);
-            if (lane == 0) sg[k] = acc;
+            if (lane == 0) {
+                if (task < r) sg[task] = acc;
+                else sdy[task - r] = yi[task - r] - acc;
+            }
         }
         __syncthreads();
-        // Gamma_r = Gamma - C^T gamma, with ||Gamma_r||^2, ||Gamma||^2 and Gamma^T x.
-        double s = 0.0, g2 = 0.0, gx = 0.0;
+        // Gamma_r = Gamma - C^T gamma, with ||Gamma_r||^2 and ||Gamma||^2.
+        double s = 0.0, g2 = 0.0, unused = 0.0;
         for (int j = tid; j < m; j += NT) {
             const double gj = sG[j];
             double acc = gj;
@@ -109,10 +120,11 @@ __global__ void __launch_bounds__(NT) k_pinv_track(const double *A, const double
             sR[j] = acc;
             s += acc * acc;
             g2 += gj * gj;
-            gx += gj * Xb[j];
         }
-        block_sum3(s, g2, gx, red);
-        if (!isfinite(g2) || !isfinite(y)) {
+        block_sum3(s, g2, unused, red);
+        bool finite_y = true;
+        for (int c = 0; c < q; ++c) finite_y = finite_y && isfinite(sdy[c]);
+        if (!isfinite(g2) || !finite_y) {
             fl |= RG_FLAG_NONFINITE;
             break;
         }
@@ -126,7 +138,6 @@ __global__ void __launch_bounds__(NT) k_pinv_track(const double *A, const double
             fl |= RG_FLAG_RANK_CAPACITY;
             break;
         }
-        const double dy = y - gx;
         // zeta = P^-1 gamma (P^-1 symmetric: column reads coalesce).
         for (int a = tid; a < r; a += NT) {
             double acc = 0.0;
@@ -134,11 +145,11 @@ __global__ void __launch_bounds__(NT) k_pinv_track(const double *A, const double
             sz[a] = acc;
         }
         __syncthreads();
-        // beta = B zeta over the i rows so far.
+        // beta = B zeta over the i rows so far (B stored transposed: the
+        // threads of a wave read consecutive rows t).
         for (int t = tid; t < i; t += NT) {
             double acc = 0.0;
-            const double *brow = Bf + (size_t)t * rmax;
-            for (int k = 0; k < r; ++k) acc += brow[k] * sz[k];
+            for (int k = 0; k < r; ++k) acc += Bf[(size_t)k * n + t] * sz[k];
             beta[t] = acc;
         }
         double den = 1.0;
@@ -171,7 +182,7 @@ __global__ void __launch_bounds__(NT) k_pinv_track(const double *A, const double
             for (int c = lane; c < i; c += 64) arow[c] -= kj * beta[c];
             if (lane == 0) arow[i] = kj;
         }
-        for (int j = tid; j < m; j += NT) Xb[j] += sK[j] * dy;
+        for (int t = tid; t < m * q; t += NT) Xb[t] += sK[t / q] * sdy[t % q];
         if (indep) {
             for (int k = wid; k < r; k += NW)
                 for (int j = lane; j < m; j += 64) Ct[(size_t)k * m + j] -= sg[k] * sK[j];
@@ -181,13 +192,13 @@ __global__ void __launch_bounds__(NT) k_pinv_track(const double *A, const double
             }
             if (tid == 0) {
                 P[(size_t)r * rmax + r] = 1.0;
-                Bf[(size_t)i * rmax + r] = 1.0;
+                Bf[(size_t)r * n + i] = 1.0;
             }
             r += 1;
         } else {
             for (int a = wid; a < r; a += NW)
                 for (int k = lane; k < r; k += 64) P[(size_t)a * rmax + k] -= sz[a] * sz[k] / den;
-            for (int k = tid; k < r; k += NT) Bf[(size_t)i * rmax + k] = sg[k];
+            for (int k = tid; k < r; k += NT) Bf[(size_t)k * n + i] = sg[k];
         }
         __syncthreads();
     }
@@ -197,7 +208,14 @@ __global__ void __launch_bounds__(NT) k_pinv_track(const double *A, const double
     }
 }
 
-size_t lds_bytes(int m, int rmax) { return sizeof(double) * (3 * (size_t)m + 2 * (size_t)rmax + 3 * NW); }
+size_t lds_bytes(int m, int rmax, int q) {
+    return sizeof(double) * (3 * (size_t)m + 2 * (size_t)rmax + (size_t)q + 3 * NW);
+}
+// beta (n doubles) joins the LDS vectors while the total stays at 64 KiB, so
+// that several workgroups still share a CU
+bool beta_fits_lds(int n, int m, int rmax, int q) {
+    return lds_bytes(m, rmax, q) + sizeof(double) * (size_t)n <= 64 * 1024;
+}
 
 constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(32) << 20;
 
@@ -235,18 +253,26 @@ extern "C" size_t rg_pinv_track_workspace_bytes(int32_t B, int32_t n, int32_t m,
     return sizeof(double) * (size_t)B * per_problem(n, m, r_max);
 }
 
-extern "C" rg_status rg_pinv_track(const double *A, const double *Y, int32_t B, int32_t n, int32_t m,
-                                   int32_t r_max, double eps, double *Ap, double *X, int32_t *rank,
-                                   uint32_t *flags, void *work, size_t work_bytes, void *stream) {
-    if (B < 1 || n < 0 || m < 1 || r_max < 1 || r_max > m || std::isnan(eps)) return RG_E_INVALID;
+extern "C" rg_status rg_pinv_track_rhs(const double *A, const double *Y, int32_t B, int32_t n, int32_t m, int32_t q,
+                                       int32_t r_max, double eps, double *Ap, double *X, int32_t *rank,
+                                       uint32_t *flags, void *work, size_t work_bytes, void *stream) {
+    if (B < 1 || n < 0 || m < 1 || q < 1 || r_max < 1 || r_max > m || std::isnan(eps)) return RG_E_INVALID;
     if (!X || !rank || !flags || !work) return RG_E_INVALID;
     if (n > 0 && (!A || !Y || !Ap)) return RG_E_INVALID;
     if (work_bytes < rg_pinv_track_workspace_bytes(B, n, m, r_max)) return RG_E_INVALID;
-    const size_t lds = lds_bytes(m, r_max);
-    if (lds > 160 * 1024) return RG_E_UNSUPPORTED;
-    hipLaunchKernelGGL(k_pinv_track, dim3(B), dim3(NT), lds, (hipStream_t)stream, A, Y, n, m, r_max, eps, Ap, X,
-                       rank, flags, (double *)work, per_problem(n, m, r_max));
+    const size_t lds0 = lds_bytes(m, r_max, q);
+    if (lds0 > 160 * 1024) return RG_E_UNSUPPORTED;
+    const bool beta_lds = beta_fits_lds(n, m, r_max, q);
+    const size_t lds = lds0 + (beta_lds ? sizeof(double) * (size_t)n : 0);
+    hipLaunchKernelGGL(k_pinv_track, dim3(B), dim3(NT), lds, (hipStream_t)stream, A, Y, n, m, q, r_max, eps, Ap, X,
+                       rank, flags, (double *)work, per_problem(n, m, r_max), beta_lds);
     return hipGetLastError() == hipSuccess ? RG_OK : RG_E_DEVICE;
+}
+
+extern "C" rg_status rg_pinv_track(const double *A, const double *Y, int32_t B, int32_t n, int32_t m,
+                                   int32_t r_max, double eps, double *Ap, double *X, int32_t *rank,
+                                   uint32_t *flags, void *work, size_t work_bytes, void *stream) {
+    return rg_pinv_track_rhs(A, Y, B, n, m, 1, r_max, eps, Ap, X, rank, flags, work, work_bytes, stream);
 }
 
 extern "C" size_t rg_pinv_track_noalloc_max_bytes(void) { return NOALLOC_SCRATCH_BYTES; }
@@ -259,7 +285,7 @@ extern "C" rg_status rg_pinv_track_noalloc(const double *A, const double *Y, int
     if (n > 0 && (!A || !Y || !Ap)) return RG_E_INVALID;
     const size_t need = rg_pinv_track_workspace_bytes(B, n, m, r_max);
     if (need > NOALLOC_SCRATCH_BYTES) return RG_E_UNSUPPORTED;
-    if (lds_bytes(m, r_max) > 160 * 1024) return RG_E_UNSUPPORTED;
+    if (lds_bytes(m, r_max, 1) > 160 * 1024) return RG_E_UNSUPPORTED;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return RG_E_DEVICE;
     void *work = scratch_address(dev);

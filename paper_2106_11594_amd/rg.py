@@ -77,6 +77,8 @@ _SIGS = {
                                      ctypes.c_size_t, _p]),
     "rg_pinv_track_noalloc": (ctypes.c_int, [_p, _p, _i32, _i32, _i32, _i32, ctypes.c_double, _p, _p, _p, _p,
                                              _p]),
+    "rg_pinv_track_rhs": (ctypes.c_int, [_p, _p, _i32, _i32, _i32, _i32, _i32, ctypes.c_double, _p, _p, _p, _p,
+                                         _p, ctypes.c_size_t, _p]),
     "rg_pinv_track_noalloc_max_bytes": (ctypes.c_size_t, []),
 }
 
@@ -450,16 +452,20 @@ def pinv_track_noalloc_max_bytes():
 
 def pinv_track(A, Y, r_max=None, eps=None, stream=None):
     """Theorems 2 and 3: push every row of A (B x n x m, or n x m) with targets
-    Y (B x n, or n) and maintain A^+ row by row (FP64, CUDA tensors).
-    Returns (Ap [B x m x n], X [B x m], rank [B] int32, flags [B] int32), with
-    the batch dimension dropped for a 2-D A.  r_max defaults to min(n, m);
-    eps=None takes the default threshold of Section 3."""
+    Y (B x n, or n; or with q right-hand sides B x n x q, or n x q) and
+    maintain A^+ row by row (FP64, CUDA tensors).  Returns (Ap [B x m x n],
+    X [B x m] or [B x m x q], rank [B] int32, flags [B] int32), with the batch
+    dimension dropped for a 2-D A.  r_max defaults to min(n, m); eps=None
+    takes the default threshold of Section 3."""
     torch = _torch()
     squeeze = A.dim() == 2
     if squeeze:
         A, Y = A.unsqueeze(0), Y.unsqueeze(0)
-    if A.dim() != 3 or Y.shape != A.shape[:2]:
-        raise ValueError("A must be B x n x m and Y B x n")
+    if A.dim() != 3 or Y.shape[:2] != A.shape[:2] or Y.dim() not in (2, 3):
+        raise ValueError("A must be B x n x m and Y B x n or B x n x q")
+    multi = Y.dim() == 3
+    q = int(Y.shape[2]) if multi else 1
+    Y = Y.contiguous()
     B, n, m = A.shape
     if r_max is None:
         r_max = max(1, min(n, m))
@@ -473,17 +479,17 @@ def pinv_track(A, Y, r_max=None, eps=None, stream=None):
     # kernel runs on, so none of them is reused while the kernel still runs
     with torch.cuda.stream(stream):
         Ap = torch.empty((B, m, n), dtype=torch.float64, device=dev)
-        X = torch.empty((B, m), dtype=torch.float64, device=dev)
+        X = torch.empty((B, m, q) if multi else (B, m), dtype=torch.float64, device=dev)
         rank = torch.empty(B, dtype=torch.int32, device=dev)
         flags = torch.empty(B, dtype=torch.int32, device=dev)
         work = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     null = ctypes.c_void_p(0)
-    _check(lib().rg_pinv_track(_dev(A, torch.float64, "A") if n else null,
-                               _dev(Y, torch.float64, "Y") if n else null, B, n, m, r_max,
-                               -1.0 if eps is None else float(eps),
-                               _dev(Ap, None, "Ap") if n else null, _dev(X, None, "X"), _dev(rank, None, "rank"),
-                               _dev(flags, None, "flags"), _dev(work, None, "work"), nbytes,
-                               ctypes.c_void_p(stream.cuda_stream)), "rg_pinv_track")
+    _check(lib().rg_pinv_track_rhs(_dev(A, torch.float64, "A") if n else null,
+                                   _dev(Y, torch.float64, "Y") if n else null, B, n, m, q, r_max,
+                                   -1.0 if eps is None else float(eps),
+                                   _dev(Ap, None, "Ap") if n else null, _dev(X, None, "X"), _dev(rank, None, "rank"),
+                                   _dev(flags, None, "flags"), _dev(work, None, "work"), nbytes,
+                                   ctypes.c_void_p(stream.cuda_stream)), "rg_pinv_track_rhs")
     if squeeze:
         return Ap[0], X[0], rank[0], flags[0]
     return Ap, X, rank, flags

@@ -222,3 +222,37 @@ def grad_batch(B=1024, m=128, r=32, n=512, seed=0, store=np.float64):
     bt = Batch(ms, np.full(B, r, np.int32), ns, row_ptr, a_off, A, Y, 1e-3, "f32")
     bt.extra["x_target"] = xt
     return bt
+
+
+# --------------------------------------------------------------------------
+# Test matrices of the stability study (Section 4.2).  Generators only: the
+# pseudoinverse references are computed by the callers.
+# --------------------------------------------------------------------------
+
+def pascal(n):
+    """Symmetric Pascal matrix P(n): P[i][j] = binomial(i + j, i) (integers)."""
+    from math import comb
+    return np.array([[comb(i + j, i) for j in range(n)] for i in range(n)], dtype=np.float64)
+
+
+def kahan(n, c):
+    """Kahan matrix K(c, s), s = sqrt(1 - c^2): upper triangular,
+    K[i][i] = s^i, K[i][j] = -c s^i for j > i."""
+    s = np.sqrt(1.0 - c * c)
+    K = np.triu(-c * np.ones((n, n)), 1) + np.eye(n)
+    return (s ** np.arange(n))[:, None] * K
+
+
+def usv(n, rows_per_col=5, seed=0):
+    """U S V^T with U (5n x n) and V (n x n) random column-orthogonal (QR of
+    Gaussians) and S = diag(2^(k/2)), k = 0..n-1; returns (A, U, S, V)."""
+    rng = _rng(5, n, seed)
+    U, _ = np.linalg.qr(rng.standard_normal((rows_per_col * n, n)))
+    V, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    S = 2.0 ** (np.arange(n) / 2.0)
+    return (U * S) @ V.T, U, S, V
+
+
+def gaussian(rows, cols, seed=0):
+    """N(0, 1) matrix (the random family R_N)."""
+    return _rng(6, rows, cols, seed).standard_normal((rows, cols))
