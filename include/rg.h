@@ -176,7 +176,11 @@ rg_status rg_batch_status(rg_handle h, int32_t *status);
  * its rows start at element gamma_off[b] of gamma (device, each stream's
  * rows row-major n_b x m_b).  row_ptr (device, B+1 int64, non-decreasing) and
  * gamma_off (device, B int64) must describe in-bounds, non-overlapping rows:
- * the library does not read them on the host.  Streams are processed
+ * the library does not read them on the host, except on a handle of one
+ * stream that runs over the whole GPU (m >= 512 and no on-chip size class
+ * holds it): there it copies row_ptr[0..1] and gamma_off[0] to the host,
+ * waiting for the handle's stream, since that path enqueues one pass of
+ * kernels per block of rows.  Streams are processed
  * concurrently in one persistent launch, largest expected cost first (see
  * rg_batch_plan). */
 rg_status rg_batch_push(rg_handle h, const void *gamma, const void *y, const int64_t *row_ptr,

@@ -66,6 +66,13 @@ int stream_class(int m, int r_max, int dtype, uint32_t opts) {
     return generic ? -1 : rg::choose_class(m, r_max, dtype);
 }
 
+// One stream that no on-chip class holds and that is large enough to spread
+// over the whole GPU (the multi-CU path, factored form).
+bool big_stream(int32_t B, int cls, int m, uint32_t opts) {
+    return B == 1 && cls < 0 && m >= rg::BIG_M_MIN &&
+           !(opts & (RG_OPT_GENERIC_KERNEL | RG_OPT_ORTHOGONAL | RG_OPT_ORTHONORMAL));
+}
+
 Layout plan_layout(int32_t B, const int32_t *m, const int32_t *r_max, size_t esize, int dtype, uint32_t opts) {
     Layout L;
     L.meta.resize(B);
@@ -79,7 +86,7 @@ Layout plan_layout(int32_t B, const int32_t *m, const int32_t *r_max, size_t esi
         M.flags = 0;
         M.cls = stream_class(M.m, M.r_max, dtype, opts);
         M.h_off = -1;
-        if (rg::class_factored(M.cls)) {
+        if (rg::class_factored(M.cls) || big_stream(B, M.cls, M.m, opts)) {
             M.h_off = (int64_t)L.h_elems;
             L.h_elems += align_up((size_t)M.r_max * M.r_max, 2);
         }
@@ -203,9 +210,23 @@ rg_status push_impl(rg_ctx *h, const void *gamma, const void *y, const int64_t *
         if (err == hipSuccess) err = e;
     }
     if (err != hipSuccess) return RG_E_DEVICE;
-    if (h->fam_count[0] > 0 && h->d_big && !row_ptr) {
+    if (h->d_big) {
+        // the multi-CU path enqueues one pass of kernels per block of rows, so
+        // it needs the row count on the host: a batched push reads its extent
         const StreamMeta &M = h->h_meta[0];
-        HIPCHK(rg::launch_push_big<T>(a, h->d_big, M.m, M.r_max, h->num_cus, h->stream));
+        const T *g0 = (const T *)gamma, *y0 = (const T *)y;
+        int64_t n = k_single;
+        if (row_ptr) {
+            int64_t rp[2], go = 0;
+            HIPCHK(hipMemcpyAsync(rp, row_ptr, sizeof(rp), hipMemcpyDeviceToHost, h->stream));
+            HIPCHK(hipMemcpyAsync(&go, goff, sizeof(go), hipMemcpyDeviceToHost, h->stream));
+            HIPCHK(hipStreamSynchronize(h->stream));
+            if (rp[1] < rp[0] || rp[0] < 0 || go < 0) return RG_E_INVALID;
+            n = rp[1] - rp[0];
+            g0 += go;
+            y0 += rp[0];
+        }
+        HIPCHK(rg::launch_push_big<T>(a, M, h->d_big, g0, y0, n, h->num_cus, h->stream));
     } else if (h->fam_count[0] > 0) {
         a.order = h->d_order + h->fam_begin[0];
         a.n_order = h->fam_count[0];
@@ -309,7 +330,7 @@ size_t rg_workspace_bytes(int32_t B, const int32_t *m, const int32_t *r_max, int
     const size_t es = dtype == RG_F64 ? 8 : 4;
     Layout L = plan_layout(B, m, r_max, es, dtype, 0);
     const StreamMeta &M0 = L.meta[0];
-    const bool big = B == 1 && M0.m >= rg::BIG_M_MIN && rg::choose_class(M0.m, M0.r_max, dtype) < 0;
+    const bool big = big_stream(B, M0.cls, M0.m, 0);
     return ws_size(L, B, es, big ? rg::big_scratch_doubles(M0.m, M0.r_max) : 0);
 }
 
@@ -360,8 +381,7 @@ static rg_status batch_init(rg_handle *out, int32_t B, const int32_t *m, const i
     }
     // one large stream that no on-chip class holds runs over the whole GPU
     const StreamMeta &M0 = h->h_meta[0];
-    const bool big = B == 1 && M0.cls < 0 && M0.m >= rg::BIG_M_MIN &&
-                     !(o.flags & (RG_OPT_GENERIC_KERNEL | RG_OPT_ORTHOGONAL | RG_OPT_ORTHONORMAL));
+    const bool big = big_stream(B, M0.cls, M0.m, o.flags);
     const size_t big_doubles = big ? rg::big_scratch_doubles(M0.m, M0.r_max) : 0;
     h->ws_bytes = ws_size(L, B, h->esize, big_doubles);
     if (user_ws) {
@@ -464,6 +484,15 @@ rg_status rg_batch_push(rg_handle h, const void *gamma, const void *y, const int
 
 rg_status rg_batch_solution(rg_handle h, void *x) {
     if (!valid_handle(h) || !x) return RG_E_INVALID;
+    if (h->d_big) {
+        const StreamMeta &M = h->h_meta[0];
+        hipError_t e = h->dtype == RG_F64
+                           ? rg::launch_solution_big<double>(h->d_meta, M, (const double *)h->d_state, h->d_h, h->d_w,
+                                                             h->d_big, (double *)x, h->stream)
+                           : rg::launch_solution_big<float>(h->d_meta, M, (const float *)h->d_state, h->d_h, h->d_w,
+                                                            h->d_big, (float *)x, h->stream);
+        return e == hipSuccess ? RG_OK : RG_E_DEVICE;
+    }
     hipError_t e = h->dtype == RG_F64
                        ? rg::launch_solution<double>(h->d_meta, h->B, (const double *)h->d_state, h->d_h, h->d_w,
                                                      (double *)x, h->rmax_max_all, h->stream)

@@ -71,11 +71,18 @@ constexpr int LDS_PROBE_BYTES_PER_THREAD_ITER = 8 * 16;
 hipError_t launch_lds_probe(float *out, int blocks, int iters, hipStream_t s);
 hipError_t launch_reset_streams(StreamMeta *meta, int B, hipStream_t s);
 // One large stream over the whole GPU (rg_big.hip): streams of single-stream
-// handles with m >= BIG_M_MIN that no on-chip class holds.
+// handles with m >= BIG_M_MIN that no on-chip class holds.  They keep the
+// dual basis in factored form (H^-1).  gam and y point at the first of the n
+// rows of the push; M is the host copy of the stream's record.
 constexpr int BIG_M_MIN = 512;
 size_t big_scratch_doubles(int m, int rmax);
 template <typename T>
-hipError_t launch_push_big(const PushArgs<T> &a, double *scratch, int m, int rmax, int num_cus, hipStream_t s);
+hipError_t launch_push_big(const PushArgs<T> &a, const StreamMeta &M, double *scratch, const T *gam, const T *y,
+                           int64_t n, int num_cus, hipStream_t s);
+// x = C^T (H^-1 w) of that stream over the whole GPU (scratch: its area).
+template <typename T>
+hipError_t launch_solution_big(const StreamMeta *meta, const StreamMeta &M, const T *state, const double *hreg,
+                               const double *wreg, double *scratch, T *x, hipStream_t s);
 template <typename T>
 hipError_t launch_pinv(const StreamMeta *meta, int B, const T *state, const double *preg, const double *hreg,
                        const T *A, const int64_t *row_ptr, const int64_t *a_off, T *Ap, int m_max, int r_max_max,

@@ -1,10 +1,12 @@
 """One large stream over the whole GPU (single-stream handles with m >= 512
-that no on-chip class holds): the edge cases of the per-row kernel chain
-against the oracle and against the one-workgroup generic kernel
-(RG_OPT_GENERIC_KERNEL) on the same rows.
+that no on-chip class holds; blocks of 16 rows through grid-wide kernels, the
+dual basis in factored form): the edge cases against the oracle, against the
+one-workgroup generic kernel (RG_OPT_GENERIC_KERNEL) and against the same
+path one row per block (RG_OPT_ROW_BY_ROW) on the same rows.
 
-Tolerances: FP64 1e-11 relative; FP32 the bound used everywhere (1e-5 for
-kappa(C) <= 1e3, else 0.1 kappa 2^-23)."""
+Tolerances: FP64 max(1e-11, kappa(C)^2 2^-52) relative (the factored form's
+H^-1 = (C C^T)^-1 carries kappa^2 rounding); FP32 the bound used everywhere
+(1e-5 for kappa(C) <= 1e3, else 0.1 kappa 2^-23)."""
 import numpy as np
 import pytest
 
@@ -19,9 +21,11 @@ def _rel(a, b):
 
 
 def _tol(dtype, C):
-    if dtype == "f64":
-        return 1e-11
     kap = float(np.linalg.cond(C)) if C.shape[0] else 1.0
+    if dtype == "f64":
+        # the factored dual basis applies H^-1 = (C C^T)^-1, whose relative
+        # error is about kappa(C)^2 2^-52 (the oracle's explicit Ct: kappa 2^-52)
+        return max(1e-11, kap * kap * 2.0 ** -52)
     return 1e-5 if kap <= 1e3 else 0.1 * kap * 2.0 ** -23
 
 
@@ -89,3 +93,64 @@ def test_big_rank_capacity_and_zero_rows():
     xo, ro, *_ = ref_c.solve(A, Y, eps=s.eps)
     assert f == 0 and r == ro == 40
     assert _rel(x, xo) <= 1e-11
+
+
+def test_big_blocked_vs_row_by_row():
+    """Blocks of 16 rows of any mix of kinds against one row per block: the
+    same ranks, and x within rounding of each other and of the oracle."""
+    from paper_2106_11594_amd import rg
+    s = W.large_stream(n=500, m=560, r=60, dtype="f64", seed=14)
+    xb, rb, fb = _solve(s.A, s.Y, "f64", s.eps, chunks=[37, 300])
+    xr, rr, fr = _solve(s.A, s.Y, "f64", s.eps, chunks=[37, 300], flags=rg.OPT_ROW_BY_ROW)
+    xo, ro, *_ = ref_c.solve(s.A, s.Y, eps=s.eps)
+    print("blocked %.2e, row by row %.2e, between %.2e" % (_rel(xb, xo), _rel(xr, xo), _rel(xb, xr)), flush=True)
+    assert fb == fr == 0 and rb == rr == ro == 60
+    assert _rel(xb, xo) <= 1e-11 and _rel(xr, xo) <= 1e-11 and _rel(xb, xr) <= 1e-11
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_big_duplicates_inside_a_block(dtype):
+    """Copies and +-1 combinations of rows of the same 16-row block while the
+    rank still grows: their Gram pivots cancel to rounding noise, which in
+    FP64 with eps = 1e-8 is as large as the threshold, so the block is
+    redone with explicit rejections.  Rank and x must match the oracle."""
+    rng = np.random.default_rng(15)
+    A = W.lowrank_rows(rng, 600, 70, 240)
+    A[5] = A[3]
+    A[9] = A[2] + A[4]
+    A[14] = A[12] - A[1]
+    A[20] = A[17]
+    A[21] = A[16] + A[19]
+    A[40:56] = A[40]  # a block of one row repeated
+    if dtype == "f32":
+        A = A.astype(np.float32).astype(np.float64)
+    Y, _ = W.targets(rng, A)
+    if dtype == "f32":
+        Y = Y.astype(np.float32).astype(np.float64)
+    eps = 1e-8 if dtype == "f64" else 1e-3
+    x, r, f = _solve(A, Y, dtype, eps)
+    xo, ro, Co, *_ = ref_c.solve(A, Y, eps=eps)
+    print("%s: rank %d/%d, rel err %.2e" % (dtype, r, ro, _rel(x, xo)), flush=True)
+    assert f == 0 and r == ro == 70
+    assert _rel(x, xo) <= _tol(dtype, Co)
+
+
+def test_big_batched_push_on_one_stream():
+    """rg_batch_push on a handle of one large stream (the host reads the row
+    extent) gives the same state as rg_push_rows."""
+    import torch
+    from paper_2106_11594_amd import rg
+    s = W.large_stream(n=300, m=640, r=40, dtype="f64", seed=16)
+    x1, r1, f1 = _solve(s.A, s.Y, "f64", s.eps, chunks=[111])  # the same blocks of rows
+    h = rg.Batch(np.array([640], np.int32), dtype="f64", eps=s.eps)
+    A = torch.from_numpy(np.ascontiguousarray(s.A)).cuda()
+    Y = torch.from_numpy(np.ascontiguousarray(s.Y)).cuda()
+    for c0, c1 in ((0, 111), (111, 300)):
+        rp = torch.tensor([0, c1 - c0], dtype=torch.int64).cuda()
+        go = torch.tensor([0], dtype=torch.int64).cuda()
+        h.push(A[c0:c1].contiguous().reshape(-1), Y[c0:c1].contiguous(), rp, go)
+    x2 = h.solution().double().cpu().numpy()
+    r2 = int(h.rank()[0])
+    h.close()
+    assert f1 == 0 and r1 == r2 == 40
+    assert np.array_equal(x1, x2)
