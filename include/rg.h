@@ -37,6 +37,13 @@
  *    definiteness on ill-conditioned bases), and the rejection, its norm, the
  *    rank decision, the Greville denominators, their reciprocals and w are
  *    FP64.  RG_F64 streams take double inputs and keep everything in FP64.
+ *  - Factored form: the streams of the blocked on-chip classes, and the
+ *    stream of a one-stream handle that no on-chip class holds (it runs in
+ *    blocks of 16 rows over the whole GPU), keep the dual basis Ct = H^-1 C
+ *    of Section 2.1 as C (the accepted input rows, exact in either element
+ *    type) and H^-1 = (C C^T)^-1 in FP64; rg_batch_get_state forms Ct on
+ *    request.  The rounding of x then grows like kappa(C)^2 2^-52 rather
+ *    than kappa(C) times the state's unit roundoff.
  */
 #ifndef RG_H
 #define RG_H
@@ -110,7 +117,10 @@ void rg_default_options(rg_options *opt);
 /* ---- one stream -------------------------------------------------------- */
 
 /* Create a stream with m regressors (m >= 1) in the empty state (rank 0,
- * x = 0, i.e. A_0^+ = 0).  opt may be NULL. */
+ * x = 0, i.e. A_0^+ = 0).  opt may be NULL.  An RG_F32 stream that an
+ * on-chip size class holds runs in one workgroup; any other stream runs in
+ * blocks of 16 rows over the whole GPU (unless RG_OPT_GENERIC_KERNEL or an
+ * orthogonal variant selects the one-workgroup generic kernel). */
 rg_status rg_init(rg_handle *out, int32_t m, const rg_options *opt);
 
 /* Push k >= 0 rows: gamma (device, k x m row-major, dtype of the handle),
@@ -177,8 +187,9 @@ rg_status rg_batch_status(rg_handle h, int32_t *status);
  * rows row-major n_b x m_b).  row_ptr (device, B+1 int64, non-decreasing) and
  * gamma_off (device, B int64) must describe in-bounds, non-overlapping rows:
  * the library does not read them on the host, except on a handle of one
- * stream that runs over the whole GPU (m >= 512 and no on-chip size class
- * holds it): there it copies row_ptr[0..1] and gamma_off[0] to the host,
+ * stream that runs over the whole GPU (no on-chip size class holds it, and
+ * neither RG_OPT_GENERIC_KERNEL nor an orthogonal variant is set): there it
+ * copies row_ptr[0..1] and gamma_off[0] to the host,
  * waiting for the handle's stream, since that path enqueues one pass of
  * kernels per block of rows.  Streams are processed
  * concurrently in one persistent launch, largest expected cost first (see

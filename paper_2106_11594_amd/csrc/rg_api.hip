@@ -66,11 +66,11 @@ int stream_class(int m, int r_max, int dtype, uint32_t opts) {
     return generic ? -1 : rg::choose_class(m, r_max, dtype);
 }
 
-// One stream that no on-chip class holds and that is large enough to spread
-// over the whole GPU (the multi-CU path, factored form).
+// A handle of one stream that no on-chip class holds runs it over the whole
+// GPU (the multi-workgroup blocked path, factored form), whatever its size.
 bool big_stream(int32_t B, int cls, int m, uint32_t opts) {
-    return B == 1 && cls < 0 && m >= rg::BIG_M_MIN &&
-           !(opts & (RG_OPT_GENERIC_KERNEL | RG_OPT_ORTHOGONAL | RG_OPT_ORTHONORMAL));
+    (void)m;
+    return B == 1 && cls < 0 && !(opts & (RG_OPT_GENERIC_KERNEL | RG_OPT_ORTHOGONAL | RG_OPT_ORTHONORMAL));
 }
 
 Layout plan_layout(int32_t B, const int32_t *m, const int32_t *r_max, size_t esize, int dtype, uint32_t opts) {

@@ -1,5 +1,6 @@
-// One large stream (m >= BIG_M_MIN, not held on chip) spread over the whole
-// GPU, in blocks of up to 16 rows.
+// The stream of a single-stream handle that no on-chip class holds (FP64
+// streams, and FP32 streams beyond the classes' m and r_max), spread over
+// the whole GPU in blocks of up to 16 rows.
 //
 // The state is the factored form of the blocked on-chip kernels: C (the
 // accepted raw rows, r x m), H^-1 = (C C^T)^-1 and P^-1 (FP64, r_max x r_max

@@ -70,11 +70,10 @@ constexpr int LDS_PROBE_THREADS = 256;
 constexpr int LDS_PROBE_BYTES_PER_THREAD_ITER = 8 * 16;
 hipError_t launch_lds_probe(float *out, int blocks, int iters, hipStream_t s);
 hipError_t launch_reset_streams(StreamMeta *meta, int B, hipStream_t s);
-// One large stream over the whole GPU (rg_big.hip): streams of single-stream
-// handles with m >= BIG_M_MIN that no on-chip class holds.  They keep the
-// dual basis in factored form (H^-1).  gam and y point at the first of the n
-// rows of the push; M is the host copy of the stream's record.
-constexpr int BIG_M_MIN = 512;
+// One stream over the whole GPU (rg_big.hip): the stream of a single-stream
+// handle that no on-chip class holds.  It keeps the dual basis in factored
+// form (H^-1).  gam and y point at the first of the n rows of the push; M is
+// the host copy of the stream's record.
 size_t big_scratch_doubles(int m, int rmax);
 template <typename T>
 hipError_t launch_push_big(const PushArgs<T> &a, const StreamMeta &M, double *scratch, const T *gam, const T *y,

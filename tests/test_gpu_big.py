@@ -1,5 +1,5 @@
-"""One large stream over the whole GPU (single-stream handles with m >= 512
-that no on-chip class holds; blocks of 16 rows through grid-wide kernels, the
+"""One stream over the whole GPU (single-stream handles that no on-chip class
+holds, here with m >= 512; blocks of 16 rows through grid-wide kernels, the
 dual basis in factored form): the edge cases against the oracle, against the
 one-workgroup generic kernel (RG_OPT_GENERIC_KERNEL) and against the same
 path one row per block (RG_OPT_ROW_BY_ROW) on the same rows.

@@ -177,10 +177,10 @@ def test_sticky_flags(dtype):
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_incremental_equals_one_push_and_deterministic(dtype):
-    """Pushing the rows in pieces gives the one-push result: bit for bit when
-    every row is taken alone (FP64 streams, RG_OPT_ROW_BY_ROW); with blocks,
-    which end at a push boundary, up to rounding.  Repeating a push sequence
-    repeats the bits."""
+    """Pushing the rows in pieces gives the one-push result: with blocks,
+    which end at a push boundary, up to rounding; bit for bit when every row
+    is taken alone (RG_OPT_ROW_BY_ROW).  Repeating a push sequence repeats
+    the bits."""
     from paper_2106_11594_amd import rg
     s = W.single_f64(n=900, m=80, r=20, seed=9)
     chunks = [0, 1, 17, 300, 301, 900]
@@ -189,13 +189,10 @@ def test_incremental_equals_one_push_and_deterministic(dtype):
     x3, h3 = _single(s.A, s.Y, dtype)
     assert h1.rank() == h2.rank() == h3.rank() == 20
     assert np.array_equal(x1, x3)
-    if dtype == "f64":
-        assert np.array_equal(x1, x2)
-    else:
-        assert _rel(x2, x1) <= 1e-5
-        xa, _ = _single(s.A, s.Y, dtype, flags=rg.OPT_ROW_BY_ROW)
-        xb, _ = _single(s.A, s.Y, dtype, chunks=chunks, flags=rg.OPT_ROW_BY_ROW)
-        assert np.array_equal(xa, xb)
+    assert _rel(x2, x1) <= (1e-11 if dtype == "f64" else 1e-5)
+    xa, _ = _single(s.A, s.Y, dtype, flags=rg.OPT_ROW_BY_ROW)
+    xb, _ = _single(s.A, s.Y, dtype, chunks=chunks, flags=rg.OPT_ROW_BY_ROW)
+    assert np.array_equal(xa, xb)
 
 
 def _batch_check(bt, dtype, eps, flags=0):
