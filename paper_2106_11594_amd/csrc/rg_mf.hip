@@ -99,16 +99,18 @@ struct MF {
     static constexpr int SPR = 17, SPS = 16 * SPR;
     static constexpr int X1_SP = 32 * NW + 64, X1_L = X1_SP + 4 * SPS, X1_C = X1_L + 256, X1_COL = X1_C + 32;
     // Waves per SIMD the register allocation is held to: two for the 4-wave
-    // variants whose LDS footprint lets two workgroups share a CU (m <= 192),
-    // which then factor column by column (a panel's registers would not fit)
+    // variants whose LDS footprint lets two workgroups share a CU (m <= 192)
     static constexpr int OCC = (NW == 4 && MMAX <= 192) ? 2 : 1;
     // HG: H^-1 stays in the stream's state in global memory (L2-resident) instead of
     // registers, where P^-1 and H^-1 together would not fit (RMAX = 128).  It is
     // only read by dependent rows, and each lane reads and writes its own tile
     // elements, in the register layout, when rows are appended.
     static constexpr bool HG = RMAX == 128;
-    static constexpr int CBW = (NW == 4 && OCC == 1) ? 4 : 1;         // Cholesky panel width (1: column by column)
     static constexpr int X1_DW = X1_COL + 96;
+    // block mode, between the projections and the rejections: per-wave partial
+    // sums of gamma^T v, ||gamma||^2, ||v||^2 (3 x 16 NW doubles in the S records' space)
+    static constexpr int X1_CT = X1_SP;
+    static_assert(3 * 16 * NW <= 4 * SPS, "room for the projection records");
     static constexpr int X1_W = X1_SP;  // independent block: W = L^-1 (row-major 16 x 16), after the records are read
     // row mode: gamma, zeta, v = C Gamma, the reduction records, Gamma_r (three separate
     // vectors, so that no row writes one that a wave may still read for the row before)
@@ -185,6 +187,7 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
     const int nq = (m + 15) / 16;         // 16-column chunks (block mode)
 
     // ---- load the state ------------------------------------------------------
+    double trh = 0.0;  // trace(C C^T) = sum of the squared norms of the rows of C
     for (int idx = t; idx < ra * CH; idx += K::NT) {
         const int k = idx / CH, c = idx - k * CH;
         float v[4];
@@ -192,8 +195,13 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
         for (int e = 0; e < 4; ++e) {
             const int j = 4 * c + e;
             v[e] = (k < r && j < m) ? Cg[(size_t)k * ldm + j] : 0.0f;
+            trh += (double)v[e] * (double)v[e];
         }
         *reinterpret_cast<float4 *>(sct + (size_t)k * MMAX + 4 * (c ^ (k & 15))) = make_float4(v[0], v[1], v[2], v[3]);
+    }
+    {
+        double z0 = 0.0, z1 = 0.0, z2 = 0.0;
+        block_sum4<NW>(trh, z0, z1, z2, smem + (size_t)ra * MMAX / 2 + K::X1_RED);
     }
     const int li = lane & 15, lg = lane >> 4;
     constexpr int NUH = K::HG ? 1 : NU, UPWH = K::HG ? 1 : UPW;
@@ -203,12 +211,18 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
     // rr read as zero), and its store (entries past rr are not written)
     auto hload = [&](int u2, int ups, int rr) -> d4 {
         if constexpr (K::HG) {
+            // unconditional loads (element 0 for entries past rr), so that the
+            // loads of several tiles are in flight together
             const int col = 16 * (wv + NW * ups) + (lane & 15);
             d4 o;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int row = 16 * u2 + 4 * v + (lane >> 4);
-                o[v] = (row < rr && col < rr) ? Hg[(size_t)row * rmax + col] : 0.0;
+                const bool in = row < rr && col < rr;
+                int64_t idx = in ? (int64_t)row * rmax + col : 0;
+                asm("" : "+v"(idx));
+                const double hv = Hg[idx];
+                o[v] = in ? hv : 0.0;
             }
             return o;
         } else {
@@ -380,15 +394,18 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
                 gacc[ups] = (d4){0.0, 0.0, 0.0, 0.0};
                 if (u < nur) {
                     if constexpr (K::HG) {
-                        // tiles of H^-1 from L2, the next one requested while the current one is multiplied
-                        d4 ht = hload(0, ups, r);
+                        // tiles of H^-1 from L2, four tiles' loads in flight at a time
 #pragma unroll 1
-                        for (int u2 = 0; u2 < nur; ++u2) {
-                            const d4 hc = ht;
-                            if (u2 + 1 < nur) ht = hload(u2 + 1, ups, r);
+                        for (int ub = 0; ub < nur; ub += 4) {
+                            d4 ht[4];
 #pragma unroll
-                            for (int v = 0; v < 4; ++v)
-                                gacc[ups] = mma(hc[v], x2[gpos<RMAX>(li, 16 * u2 + 4 * v + lg)], gacc[ups]);
+                            for (int q = 0; q < 4; ++q) ht[q] = hload(ub + q, ups, r);
+#pragma unroll
+                            for (int q = 0; q < 4; ++q)
+                                if (ub + q < nur)
+#pragma unroll
+                                    for (int v = 0; v < 4; ++v)
+                                        gacc[ups] = mma(ht[q][v], x2[gpos<RMAX>(li, 16 * (ub + q) + 4 * v + lg)], gacc[ups]);
                         }
                     } else {
 #pragma unroll
@@ -400,6 +417,21 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
                                     gacc[ups] = mma(ht[v], x2[gpos<RMAX>(li, 16 * u2 + 4 * v + lg)], gacc[ups]);
                             }
                         }
+                    }
+                }
+            }
+            // this wave's parts of gamma_i^T v_i, ||gamma_i||^2 and ||v_i||^2 (V is still in X2)
+            double pgv = 0.0, pgg = 0.0, pvv = 0.0;
+#pragma unroll
+            for (int ups = 0; ups < UPW; ++ups) {
+                const int u = wv + NW * ups;
+                if (u < nur) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const double vv = x2[gpos<RMAX>(li, 16 * u + 4 * v + lg)];
+                        pgv += gacc[ups][v] * vv;
+                        pgg += gacc[ups][v] * gacc[ups][v];
+                        pvv += vv * vv;
                     }
                 }
             }
@@ -417,7 +449,40 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
                 }
             }
             gwp = sum_rows(gwp);
+            pgv = sum_rows(pgv);
+            pgg = sum_rows(pgg);
+            pvv = sum_rows(pvv);
+            if (lg == 0) {
+                x1[K::X1_CT + 16 * wv + li] = pgv;
+                x1[K::X1_CT + 16 * NW + 16 * wv + li] = pgg;
+                x1[K::X1_CT + 32 * NW + 16 * wv + li] = pvv;
+            }
             __syncthreads();
+
+            // ---- rows that are dependent beyond doubt ----
+            // ||R_i||^2 = ||Gamma_i||^2 - gamma_i^T v_i in exact arithmetic.  Its
+            // rounding is bounded by 2^-52 (8 ||Gamma_i||^2 + 4 r ||gamma_i|| ||v_i||
+            // + 64 r trace(C C^T) ||gamma_i||^2): the last term covers H^-1 as the
+            // inverse of C C^T perturbed by a few r units of roundoff relative to
+            // its norm.  When this bound keeps every row of the block below the
+            // rank threshold of Section 3, all rows are dependent and the
+            // rejections are not formed; otherwise they are, as below.
+            bool skip_r;
+            {
+                double cgv = 0.0, cgg = 0.0, cvv = 0.0;
+#pragma unroll
+                for (int q = 0; q < NW; ++q) {
+                    cgv += x1[K::X1_CT + 16 * q + li];
+                    cgg += x1[K::X1_CT + 16 * NW + 16 * q + li];
+                    cvv += x1[K::X1_CT + 32 * NW + 16 * q + li];
+                }
+                const double eps0 = a.eps >= 0.0 ? a.eps : ((double)m * m * r + (double)m * r + (double)m) * 0x1p-52;
+                const double est = gsq - cgv;
+                const double bnd = 0x1p-52 * (8.0 * gsq + 4.0 * r * sqrt(cgg * cvv) + 64.0 * r * trh * cgg);
+                const bool sure = li >= nblk ||
+                                  (isfinite(gsq) && isfinite(yrow) && est + bnd < eps0 * eps0 * fmax(1.0, gsq));
+                skip_r = (__ballot(!sure) & 0xFFFFull) == 0;
+            }
 
             // ---- R^T = Gamma_blk^T - C^T G^T, ||R_i||^2 and this wave's part of R R^T ----
             double rsq = 0.0;
@@ -425,7 +490,7 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
 #pragma unroll
             for (int tau = 0; tau < TPW; ++tau) {
                 const int ct = wv + NW * tau;
-                if (ct < nq) {
+                if (ct < nq && !skip_r) {
                     d4 d = (d4){gi[tau][0], gi[tau][1], gi[tau][2], gi[tau][3]};
                     if constexpr (K::HG) {
 #pragma unroll 1
@@ -556,15 +621,13 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
             __syncthreads();
 
             // ---- Cholesky S = L L^T (lane i holds row i), c = L^-1 (y - G w) ----
-            // Wave 0 factors S = L L^T (lane i holds row i) in panels of CBW columns:
-            // the panel's columns and the running value of L^-1 (y - G w) are shared
-            // through LDS once per panel (LDS accesses of one wave are performed in
-            // program order, so no barrier is needed), every lane factors the panel
-            // from the shared copy, then updates its own row past the panel.  A pivot
-            // that is not positive and finite ends the prefix of applied rows (ndd);
-            // what follows it is computed but never used.
+            // Wave 0 factors S column by column, lane i holding row i (the four
+            // DPP rows of the wave hold copies).  Column k of the trailing matrix
+            // is broadcast from the lanes that hold it (lane reads, no LDS round
+            // trip), every lane scales and updates its own row.  A pivot that is
+            // not positive and finite ends the prefix of applied rows (ndd); what
+            // follows it is computed but never used.
             if (wv == 0) {
-                constexpr int CBW = K::CBW;
                 double srow[16];
 #pragma unroll
                 for (int cc = 0; cc < 16; ++cc) srow[cc] = (cc == li && !indblk) ? 1.0 : 0.0;
@@ -575,29 +638,16 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
                 }
                 double cy = rowok ? dyi : 0.0;
                 double mypiv = 1.0, myc = 0.0, myinv = 0.0;
-                double *col = x1 + K::X1_COL;
-                if constexpr (CBW == 1) {
 #pragma unroll
                 for (int k = 0; k < 16; ++k) {
-                    col[li] = srow[k];
-                    col[16 + li] = cy;
-                    __builtin_amdgcn_wave_barrier();
-                    double cv[16];  // column k, read with wide loads issued back to back
+                    double cv[16];  // column k: S[j][k] on lane j, j >= k
 #pragma unroll
-                    for (int q = k / 2; q < 8; ++q) {
-                        const double2 v2 = reinterpret_cast<const double2 *>(col)[q];
-                        cv[2 * q] = v2.x;
-                        cv[2 * q + 1] = v2.y;
-                    }
-                    const double cyk = col[16 + k];
-                    __builtin_amdgcn_wave_barrier();  // this step's loads before the next step's stores
+                    for (int j = k; j < 16; ++j) cv[j] = read_lane(srow[k], j);
+                    const double cyk = read_lane(cy, k);
                     const double piv = cv[k];
                     const double inv = rsqrt_f64(piv), lkk = piv * inv;
                     const double ck = cyk * inv;
                     const double lik = srow[k] * inv;  // L[i][k] for i > k
-                    double ljk[16];
-#pragma unroll
-                    for (int j = k + 1; j < 16; ++j) ljk[j] = cv[j] * inv;
                     if (li == k) {
                         mypiv = piv;
                         myc = ck;
@@ -606,65 +656,7 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
                     srow[k] = li == k ? lkk : (li > k ? lik : 0.0);
                     if (li > k) cy -= lik * ck;
 #pragma unroll
-                    for (int j = k + 1; j < 16; ++j) srow[j] -= lik * ljk[j];
-                }
-                } else {
-#pragma unroll
-                for (int kb = 0; kb < 16; kb += CBW) {
-                    if (lg == 0) {
-#pragma unroll
-                        for (int q = 0; q < CBW; ++q) col[16 * q + li] = srow[kb + q];
-                        col[16 * CBW + li] = cy;
-                    }
-                    __builtin_amdgcn_wave_barrier();
-                    double pc[CBW][16], cyv[CBW];  // pc[q][j] = S[j][kb + q] at the panel start (j >= kb)
-#pragma unroll
-                    for (int q = 0; q < CBW; ++q)
-#pragma unroll
-                        for (int h2 = kb / 2; h2 < 8; ++h2) {
-                            const double2 v2 = reinterpret_cast<const double2 *>(col + 16 * q)[h2];
-                            pc[q][2 * h2] = v2.x;
-                            pc[q][2 * h2 + 1] = v2.y;
-                        }
-#pragma unroll
-                    for (int q = 0; q < CBW; ++q) cyv[q] = col[16 * CBW + kb + q];
-                    __builtin_amdgcn_wave_barrier();  // this panel's loads before the next panel's stores
-                    double lik[CBW];
-#pragma unroll
-                    for (int q = 0; q < CBW; ++q) {
-                        const int k = kb + q;
-                        const double piv = pc[q][k];
-                        const double inv = rsqrt_f64(piv), lkk = piv * inv;
-#pragma unroll
-                        for (int j = k; j < 16; ++j) pc[q][j] *= inv;  // column k of L, rows j >= k
-                        const double ck = cyv[q] * inv;
-                        lik[q] = srow[k] * inv;
-                        if (li == k) {
-                            mypiv = piv;
-                            myc = ck;
-                            myinv = inv;
-                        }
-                        srow[k] = li == k ? lkk : (li > k ? lik[q] : 0.0);
-                        if (li > k) cy -= lik[q] * ck;
-#pragma unroll
-                        for (int q2 = q + 1; q2 < CBW; ++q2) cyv[q2] -= pc[q][kb + q2] * ck;
-#pragma unroll
-                        for (int q2 = q + 1; q2 < CBW; ++q2) {
-                            const int k2 = kb + q2;
-                            const double f = pc[q][k2];  // L[k2][k]
-#pragma unroll
-                            for (int j = k2; j < 16; ++j) pc[q2][j] -= pc[q][j] * f;
-                            srow[k2] -= lik[q] * f;
-                        }
-                    }
-#pragma unroll
-                    for (int j = kb + CBW; j < 16; ++j) {
-                        double acc = srow[j];
-#pragma unroll
-                        for (int q = 0; q < CBW; ++q) acc -= lik[q] * pc[q][j];
-                        srow[j] = acc;
-                    }
-                }
+                    for (int j = k + 1; j < 16; ++j) srow[j] -= lik * (cv[j] * inv);
                 }
                 if (!indblk) {
                 const uint64_t badp = __ballot(!(mypiv > 0.0 && isfinite(mypiv))) & 0xFFFFull;
@@ -831,6 +823,8 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
                         }
                     }
                 }
+#pragma unroll 1
+                for (int j = 0; j < ni; ++j) trh += x1[K::X1_GG + j];
                 r = r0 + ni;
                 i += ni;
                 applied += ni;
@@ -1135,6 +1129,7 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
                 }
             }
             r += 1;
+            trh += g2;
             block_mode = ind_blocks;
             __syncthreads();
         }
