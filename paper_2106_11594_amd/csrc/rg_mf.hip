@@ -330,8 +330,9 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
             d4 gacc[UPW];
             double gsq = 0.0;
             {
+                d4 gacc2[UPW];
 #pragma unroll
-                for (int ups = 0; ups < UPW; ++ups) gacc[ups] = (d4){0.0, 0.0, 0.0, 0.0};
+                for (int ups = 0; ups < UPW; ++ups) gacc[ups] = gacc2[ups] = (d4){0.0, 0.0, 0.0, 0.0};
                 // chunk 4q + g of a row with (row & 15) == i sits at physical chunk (4q + g) ^ i;
                 // the operands of chunk q + 1 are loaded while chunk q is multiplied
                 const float *gbase = x1f + li * MMAX;
@@ -362,13 +363,16 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
 #pragma unroll
                     for (int ups = 0; ups < UPW; ++ups) {
                         if (wv + NW * ups < nur) {
+                            // two accumulators, so that consecutive products do not wait on each other
                             gacc[ups] = mma((double)cq[ups].x, b0, gacc[ups]);
-                            gacc[ups] = mma((double)cq[ups].y, b1, gacc[ups]);
+                            gacc2[ups] = mma((double)cq[ups].y, b1, gacc2[ups]);
                             gacc[ups] = mma((double)cq[ups].z, b2, gacc[ups]);
-                            gacc[ups] = mma((double)cq[ups].w, b3, gacc[ups]);
+                            gacc2[ups] = mma((double)cq[ups].w, b3, gacc2[ups]);
                         }
                     }
                 }
+#pragma unroll
+                for (int ups = 0; ups < UPW; ++ups) gacc[ups] += gacc2[ups];
             }
             gsq = sum_rows(gsq);  // ||Gamma_i||^2
 #pragma unroll
@@ -393,19 +397,23 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
                 const int u = wv + NW * ups;
                 gacc[ups] = (d4){0.0, 0.0, 0.0, 0.0};
                 if (u < nur) {
+                    d4 g2acc = (d4){0.0, 0.0, 0.0, 0.0};
                     if constexpr (K::HG) {
-                        // tiles of H^-1 from L2, four tiles' loads in flight at a time
+                        // tiles of H^-1 from L2, HB tiles' loads in flight at a time
+                        constexpr int HB = 4;
 #pragma unroll 1
-                        for (int ub = 0; ub < nur; ub += 4) {
-                            d4 ht[4];
+                        for (int ub = 0; ub < nur; ub += HB) {
+                            d4 ht[HB];
 #pragma unroll
-                            for (int q = 0; q < 4; ++q) ht[q] = hload(ub + q, ups, r);
+                            for (int q = 0; q < HB; ++q) ht[q] = hload(ub + q, ups, r);
 #pragma unroll
-                            for (int q = 0; q < 4; ++q)
+                            for (int q = 0; q < HB; ++q)
                                 if (ub + q < nur)
 #pragma unroll
-                                    for (int v = 0; v < 4; ++v)
+                                    for (int v = 0; v < 4; v += 2) {
                                         gacc[ups] = mma(ht[q][v], x2[gpos<RMAX>(li, 16 * (ub + q) + 4 * v + lg)], gacc[ups]);
+                                        g2acc = mma(ht[q][v + 1], x2[gpos<RMAX>(li, 16 * (ub + q) + 4 * v + 4 + lg)], g2acc);
+                                    }
                         }
                     } else {
 #pragma unroll
@@ -413,11 +421,14 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
                             if (u2 < nur) {
                                 const d4 ht = hload(u2, ups, r);
 #pragma unroll
-                                for (int v = 0; v < 4; ++v)
+                                for (int v = 0; v < 4; v += 2) {
                                     gacc[ups] = mma(ht[v], x2[gpos<RMAX>(li, 16 * u2 + 4 * v + lg)], gacc[ups]);
+                                    g2acc = mma(ht[v + 1], x2[gpos<RMAX>(li, 16 * u2 + 4 * v + 4 + lg)], g2acc);
+                                }
                             }
                         }
                     }
+                    gacc[ups] += g2acc;
                 }
             }
             // this wave's parts of gamma_i^T v_i, ||gamma_i||^2 and ||v_i||^2 (V is still in X2)
@@ -584,16 +595,20 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
                 const int u = wv + NW * ups;
                 z[ups] = (d4){0.0, 0.0, 0.0, 0.0};
                 if (u < nur) {
+                    d4 z2 = (d4){0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                     for (int u2 = 0; u2 < NU; ++u2) {
                         if (u2 < nur) {
 #pragma unroll
-                            for (int v = 0; v < 4; ++v) {
-                                const double gb = rowok ? x2[gpos<RMAX>(li, 16 * u2 + 4 * v + lg)] : 0.0;
-                                z[ups] = mma(p[u2][ups][v], gb, z[ups]);
+                            for (int v = 0; v < 4; v += 2) {
+                                const double gb0 = x2[gpos<RMAX>(li, 16 * u2 + 4 * v + lg)];
+                                const double gb1 = x2[gpos<RMAX>(li, 16 * u2 + 4 * v + 4 + lg)];
+                                z[ups] = mma(p[u2][ups][v], rowok ? gb0 : 0.0, z[ups]);
+                                z2 = mma(p[u2][ups][v + 1], rowok ? gb1 : 0.0, z2);
                             }
                         }
                     }
+                    z[ups] += z2;
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
                         const double ga = rowok ? x2[gpos<RMAX>(li, 16 * u + 4 * v + lg)] : 0.0;
