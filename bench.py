@@ -60,10 +60,12 @@ def kernel_digest():
 def measured_traffic(B):
     """HBM bytes of one push from the committed counter summary (FETCH_SIZE +
     WRITE_SIZE of the push kernels, each scaled by the ratio of the known
-    size of a plain copy to what the same counter read for it), or None when
-    the summary is missing or was taken on other kernel sources or another
-    workload.  Counter collection serialises the dispatches, so the figure is
-    the same for concurrent and serial class launches."""
+    size of a plain copy to what the same counter read for it): a dict with
+    the total and the bytes of each push kernel (keyed "k_push_mf<RMAX,MMAX,
+    waves>"), or None when the summary is missing or was taken on other
+    kernel sources or another workload.  Counter collection serialises the
+    dispatches, so the figures are the same for concurrent and serial class
+    launches and for a class pushed alone."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as f:
@@ -75,7 +77,10 @@ def measured_traffic(B):
         return None
     if rec.get("kernel_digest") != kernel_digest() or rec.get("streams") != B:
         return None
-    return float(rec["fetch_kib"]) * 1024 * rec["fetch_scale"] + float(rec["write_kib"]) * 1024 * rec["write_scale"]
+    per = {k: float(v[0]) * 1024 * rec["fetch_scale"] + float(v[1]) * 1024 * rec["write_scale"]
+           for k, v in rec.get("per_kernel_kib", {}).items()}
+    total = float(rec["fetch_kib"]) * 1024 * rec["fetch_scale"] + float(rec["write_kib"]) * 1024 * rec["write_scale"]
+    return {"total": total, "per_kernel": per}
 
 
 def headroom(m, r, cap=128):
@@ -413,7 +418,7 @@ def main():
     roof = {"bound": "lds", "peak": lds_gbs, "unit": "GB/s",
             "peak_source": "LDS read probe of the library (rg_probe_lds_read), %d workgroups x %d iterations, "
                            "best of 5, measured in this run" % (lds_blocks, lds_iters),
-            "traffic": traffic}
+            "traffic": None}
     if per_class:
         dom = max(per_class, key=lambda c: per_class[c]["launch_ms"])
         pc = per_class[dom]
@@ -425,10 +430,14 @@ def main():
                      "algorithmic_flops_per_launch": pc["algorithmic_flops"],
                      "fp64_mfma_frac": pc["algorithmic_flops"] / (pc["launch_ms"] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS})
         roof["frac"] = roof["achieved"] / lds_gbs
+        if traffic is not None and dom >= 3:
+            roof["traffic"] = traffic["per_kernel"].get("k_push_mf<%s,%s,%d>" % (pc["r_max_cap"], pc["m_cap"],
+                                                                                   pc["threads"] // 64))
     whole = {"launch_ms": push_ms, "algorithmic_state_bytes": byts, "algorithmic_flops": flops,
              "state_bytes_rate_GBs": byts / (push_ms * 1e-3) / 1e9,
              "lds_frac": byts / (push_ms * 1e-3) / 1e9 / lds_gbs,
              "fp64_mfma_frac": flops / (push_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+             "hbm_traffic_bytes": None if traffic is None else traffic["total"],
              "note": "all classes concurrently, eager push (reset + push), HIP events"}
 
     out = {"metric": METRIC, "value": value, "unit": "row-updates/s", "n_gpus": 1, "steps": args.steps,
