@@ -95,6 +95,10 @@ typedef enum { RG_F32 = 0, RG_F64 = 1 } rg_dtype;
                                           instead of the persistent grid (as many workgroups
                                           as fit on the chip, each taking streams from a
                                           queue, longest expected cost first) */
+#define RG_OPT_EXPLICIT_REJECTIONS 0x100u  /* blocked on-chip classes: always form the
+                                    rejections of a block, also when every row of it is
+                                    dependent beyond doubt from ||Gamma||^2 - gamma^T v and
+                                    its rounding bound (testing; results agree to rounding) */
 
 typedef struct {
     int32_t dtype;   /* rg_dtype */

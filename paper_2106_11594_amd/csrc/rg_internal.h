@@ -32,6 +32,7 @@ constexpr uint32_t OPT_DEPENDENT_BLOCKS_ONLY = 0x10u;
 constexpr uint32_t OPT_ORTHOGONAL = 0x20u;
 constexpr uint32_t OPT_ORTHONORMAL = 0x40u;
 constexpr uint32_t OPT_ONE_WG_PER_STREAM = 0x80u;
+constexpr uint32_t OPT_EXPLICIT_REJECTIONS = 0x100u;
 
 // Arguments of a push launch (by value).
 template <typename T>

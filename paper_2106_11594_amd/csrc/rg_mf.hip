@@ -492,7 +492,7 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
                 const double bnd = 0x1p-52 * (8.0 * gsq + 4.0 * r * sqrt(cgg * cvv) + 64.0 * r * trh * cgg);
                 const bool sure = li >= nblk ||
                                   (isfinite(gsq) && isfinite(yrow) && est + bnd < eps0 * eps0 * fmax(1.0, gsq));
-                skip_r = (__ballot(!sure) & 0xFFFFull) == 0;
+                skip_r = (__ballot(!sure) & 0xFFFFull) == 0 && !(a.opts & OPT_EXPLICIT_REJECTIONS);
             }
 
             // ---- R^T = Gamma_blk^T - C^T G^T, ||R_i||^2 and this wave's part of R R^T ----

@@ -21,6 +21,7 @@ OPT_NO_REPROJECT, OPT_GENERIC_KERNEL, OPT_SERIAL_CLASSES, OPT_ROW_BY_ROW = 0x1, 
 OPT_DEPENDENT_BLOCKS_ONLY = 0x10
 OPT_ORTHOGONAL, OPT_ORTHONORMAL = 0x20, 0x40
 OPT_ONE_WG_PER_STREAM = 0x80
+OPT_EXPLICIT_REJECTIONS = 0x100
 OK, E_INVALID, E_NOMEM, E_DEVICE, E_RANK_CAPACITY, E_NONFINITE, E_STATE, E_UNSUPPORTED = range(8)
 _STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "HIP runtime error", 4: "rank capacity reached",
            5: "non-finite row or target", 6: "stream is flagged", 7: "unsupported size"}

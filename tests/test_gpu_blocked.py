@@ -234,3 +234,32 @@ def test_persistent_grid_equals_one_workgroup_per_stream():
     assert (ra == rb).all() and (fa == fb).all() and (fa == 0).all()
     for b in range(bt.B):
         assert np.array_equal(xa[b], xb[b]), b
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_certified_skip_vs_explicit_rejections(dtype):
+    """Blocks whose rows are all dependent beyond doubt (the bound on
+    ||Gamma||^2 - gamma^T v below the threshold with its rounding error
+    included) skip the explicit rejections; RG_OPT_EXPLICIT_REJECTIONS forms
+    them anyway.  On 49 streams of the batched workload, most of whose rows
+    come after the rank has filled, both give the oracle's rank and x within
+    rounding of each other and within the factored form's bound of the
+    oracle."""
+    from paper_2106_11594_amd import rg
+    from tests.gpu_util import run_batch
+    bt = W.batched(streams=np.arange(7, 4096, 85), dtype=dtype)
+    xs, r1, f1, _ = run_batch(bt, dtype)
+    xe, r2, f2, _ = run_batch(bt, dtype, flags=rg.OPT_EXPLICIT_REJECTIONS)
+    assert (f1 == 0).all() and (f2 == 0).all()
+    worst = between = 0.0
+    for k in range(bt.B):
+        A, Y = bt.stream(k)
+        xo, ro, Co, *_ = ref_c.solve(A, Y, eps=bt.eps)
+        assert r1[k] == r2[k] == ro, k
+        tol = _kappa_tol(Co)[0] if dtype == "f32" else max(1e-11, float(np.linalg.cond(Co)) ** 2 * 2.0 ** -52)
+        e1, e2, eb = _rel(xs[k], xo), _rel(xe[k], xo), _rel(xs[k], xe[k])
+        assert e1 <= tol and e2 <= tol, (k, e1, e2, tol)
+        assert eb <= tol, (k, eb)
+        worst, between = max(worst, e1, e2), max(between, eb)
+    print("%s: worst vs oracle %.2e, between the modes %.2e" % (dtype, worst, between), flush=True)
