@@ -108,9 +108,10 @@ struct MF {
     static constexpr bool HG = RMAX == 128;
     static constexpr int X1_DW = X1_COL + 96;
     // block mode, between the projections and the rejections: per-wave partial
-    // sums of gamma^T v, ||gamma||^2, ||v||^2 (3 x 16 NW doubles in the S records' space)
+    // sums of gamma^T v, ||gamma||^2, ||v||^2 and ||Gamma||^2 (4 x 16 NW doubles in
+    // the S records' space)
     static constexpr int X1_CT = X1_SP;
-    static_assert(3 * 16 * NW <= 4 * SPS, "room for the projection records");
+    static_assert(4 * 16 * NW <= 4 * SPS, "room for the projection records");
     static constexpr int X1_W = X1_SP;  // independent block: W = L^-1 (row-major 16 x 16), after the records are read
     // row mode: gamma, zeta, v = C Gamma, the reduction records, Gamma_r (three separate
     // vectors, so that no row writes one that a wave may still read for the row before)
@@ -162,7 +163,9 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
     float *x1f = reinterpret_cast<float *>(x1);   // block rows, 16 x MMAX, swizzled like C
     float *ring = reinterpret_cast<float *>(x2);  // row mode: 3 rows of MMAX
 
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    // the wave index is uniform over the wave: held in a scalar register, so that
+    // branches and addresses that depend only on it are scalar
+    const int t = threadIdx.x, lane = t & 63, wv = __builtin_amdgcn_readfirstlane(t >> 6);
     StreamMeta *M = a.meta + b_id;
     const int m = M->m, rmax = M->r_max, ldm = M->ldm;
     int r = M->r;
@@ -209,22 +212,35 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
     double wr[UPW][4];
     // Tile (u2, u = wv + NW ups) of H^-1 for the current rank rr (entries past
     // rr read as zero), and its store (entries past rr are not written)
+    // Raw tile loads (HG): unconditional, element 0 for entries past rr, so that
+    // the loads of several tiles are in flight together; hmask zeroes those
+    // entries where the tile is used.
+    auto hraw = [&](int u2, int ups, int rr) -> d4 {
+        const int col = 16 * (wv + NW * ups) + (lane & 15);
+        d4 o;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = 16 * u2 + 4 * v + (lane >> 4);
+            const bool in = row < rr && col < rr;
+            int64_t idx = in ? (int64_t)row * rmax + col : 0;
+            asm("" : "+v"(idx));
+            o[v] = Hg[idx];
+        }
+        return o;
+    };
+    auto hmask = [&](int u2, int ups, int rr, const d4 &raw) -> d4 {
+        const int col = 16 * (wv + NW * ups) + (lane & 15);
+        d4 o;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = 16 * u2 + 4 * v + (lane >> 4);
+            o[v] = row < rr && col < rr ? raw[v] : 0.0;
+        }
+        return o;
+    };
     auto hload = [&](int u2, int ups, int rr) -> d4 {
         if constexpr (K::HG) {
-            // unconditional loads (element 0 for entries past rr), so that the
-            // loads of several tiles are in flight together
-            const int col = 16 * (wv + NW * ups) + (lane & 15);
-            d4 o;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = 16 * u2 + 4 * v + (lane >> 4);
-                const bool in = row < rr && col < rr;
-                int64_t idx = in ? (int64_t)row * rmax + col : 0;
-                asm("" : "+v"(idx));
-                const double hv = Hg[idx];
-                o[v] = in ? hv : 0.0;
-            }
-            return o;
+            return hmask(u2, ups, rr, hraw(u2, ups, rr));
         } else {
             return h[u2][ups];
         }
@@ -359,7 +375,7 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
                             if (wv + NW * ups < nur) ca[ups] = *reinterpret_cast<const float4 *>(cbase[ups] + 4 * phn);
                     }
                     const double b0 = gq.x, b1 = gq.y, b2 = gq.z, b3 = gq.w;
-                    gsq += b0 * b0 + b1 * b1 + b2 * b2 + b3 * b3;
+                    if ((q & (NW - 1)) == wv) gsq += b0 * b0 + b1 * b1 + b2 * b2 + b3 * b3;  // this wave's share
 #pragma unroll
                     for (int ups = 0; ups < UPW; ++ups) {
                         if (wv + NW * ups < nur) {
@@ -374,7 +390,9 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
 #pragma unroll
                 for (int ups = 0; ups < UPW; ++ups) gacc[ups] += gacc2[ups];
             }
-            gsq = sum_rows(gsq);  // ||Gamma_i||^2
+            // this wave's share of ||Gamma_i||^2 (chunks wv, wv + NW, ...); the
+            // shares are summed after the projections, in a fixed order
+            gsq = sum_rows(gsq);
 #pragma unroll
             for (int ups = 0; ups < UPW; ++ups) {
                 const int u = wv + NW * ups;
@@ -467,6 +485,7 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
                 x1[K::X1_CT + 16 * wv + li] = pgv;
                 x1[K::X1_CT + 16 * NW + 16 * wv + li] = pgg;
                 x1[K::X1_CT + 32 * NW + 16 * wv + li] = pvv;
+                x1[K::X1_CT + 48 * NW + 16 * wv + li] = gsq;
             }
             __syncthreads();
 
@@ -481,11 +500,13 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
             bool skip_r;
             {
                 double cgv = 0.0, cgg = 0.0, cvv = 0.0;
+                gsq = 0.0;  // ||Gamma_i||^2
 #pragma unroll
                 for (int q = 0; q < NW; ++q) {
                     cgv += x1[K::X1_CT + 16 * q + li];
                     cgg += x1[K::X1_CT + 16 * NW + 16 * q + li];
                     cvv += x1[K::X1_CT + 32 * NW + 16 * q + li];
+                    gsq += x1[K::X1_CT + 48 * NW + 16 * q + li];
                 }
                 const double eps0 = a.eps >= 0.0 ? a.eps : ((double)m * m * r + (double)m * r + (double)m) * 0x1p-52;
                 const double est = gsq - cgv;
@@ -642,15 +663,26 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
             // trip), every lane scales and updates its own row.  A pivot that is
             // not positive and finite ends the prefix of applied rows (ndd); what
             // follows it is computed but never used.
+            // Z to LDS for the substitution (every read of G ended at the barrier
+            // above), before the factorization, so that Z need not stay in registers
+            if (!indblk) {
+#pragma unroll
+                for (int ups = 0; ups < UPW; ++ups) {
+                    const int u = wv + NW * ups;
+                    if (u < nur) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) x2[zpos(16 * u + 4 * v + lg, li)] = z[ups][v];
+                    }
+                }
+            }
             if (wv == 0) {
+                // row li of S: lane group lg reads row li of record lg (all loads in
+                // flight together), and the four lane groups are summed
                 double srow[16];
 #pragma unroll
-                for (int cc = 0; cc < 16; ++cc) srow[cc] = (cc == li && !indblk) ? 1.0 : 0.0;
-#pragma unroll 1
-                for (int q = 0; q < 4; ++q) {
+                for (int cc = 0; cc < 16; ++cc) srow[cc] = x1[K::X1_SP + K::SPS * lg + K::SPR * li + cc];
 #pragma unroll
-                    for (int cc = 0; cc < 16; ++cc) srow[cc] += x1[K::X1_SP + K::SPS * q + K::SPR * li + cc];
-                }
+                for (int cc = 0; cc < 16; ++cc) srow[cc] = sum_rows(srow[cc]) + ((cc == li && !indblk) ? 1.0 : 0.0);
                 double cy = rowok ? dyi : 0.0;
                 double mypiv = 1.0, myc = 0.0, myinv = 0.0;
 #pragma unroll
@@ -728,22 +760,11 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
                     }
                 }
             }
-            // Z to LDS for the substitution (every read of G ended at the barrier above)
-            if (!indblk) {
-#pragma unroll
-                for (int ups = 0; ups < UPW; ++ups) {
-                    const int u = wv + NW * ups;
-                    if (u < nur) {
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) x2[zpos(16 * u + 4 * v + lg, li)] = z[ups][v];
-                    }
-                }
-            }
             __syncthreads();
             if (indblk) {
                 // ---- independent rows 0 .. ni-1 of the block: H^-1 += U U^T with
                 //      U = [G^T W^T; -W^T], appends to C, P^-1 and w ----
-                const int ni = (int)x1[K::X1_COL];
+                const int ni = __builtin_amdgcn_readfirstlane((int)x1[K::X1_COL]);
                 const bool nonf = x1[K::X1_COL + 1] != 0.0;
                 if (ni == 0) {
                     // the first row failed the pivot test although its rejection passed
@@ -790,7 +811,13 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
                     const float *src = G0 + (i - i0 + j) * (int64_t)m;
                     float v[4];
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) v[e] = 4 * cc + e < m ? src[4 * cc + e] : 0.0f;
+                    for (int e = 0; e < 4; ++e) {
+                        // unconditional loads (column 0 past m), all in flight together
+                        int col = 4 * cc + e < m ? 4 * cc + e : 0;
+                        asm("" : "+v"(col));
+                        const float x = src[col];
+                        v[e] = 4 * cc + e < m ? x : 0.0f;
+                    }
                     *reinterpret_cast<float4 *>(sct + (size_t)k * MMAX + 4 * (cc ^ (k & 15))) =
                         make_float4(v[0], v[1], v[2], v[3]);
                 }
@@ -803,12 +830,20 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
 #pragma unroll
                         for (int ks = 0; ks < 4; ++ks) bt[ks] = x2[zpos(16 * u + li, 4 * ks + lg)];
                         if constexpr (K::HG) {
+                            // four tiles' loads in flight at a time
 #pragma unroll 1
-                            for (int u2 = 0; u2 < nurn; ++u2) {
-                                d4 acc = hload(u2, ups, r0);
+                            for (int ub = 0; ub < nurn; ub += 4) {
+                                d4 acc[4];
 #pragma unroll
-                                for (int ks = 0; ks < 4; ++ks) acc = mma(x2[zpos(16 * u2 + li, 4 * ks + lg)], bt[ks], acc);
-                                hstore(u2, ups, acc, r0 + ni);
+                                for (int q = 0; q < 4; ++q) acc[q] = hload(ub + q, ups, r0);
+#pragma unroll
+                                for (int q = 0; q < 4; ++q)
+                                    if (ub + q < nurn) {
+#pragma unroll
+                                        for (int ks = 0; ks < 4; ++ks)
+                                            acc[q] = mma(x2[zpos(16 * (ub + q) + li, 4 * ks + lg)], bt[ks], acc[q]);
+                                        hstore(ub + q, ups, acc[q], r0 + ni);
+                                    }
                             }
                         } else {
 #pragma unroll
@@ -830,7 +865,7 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
                         const int kk = 16 * u + 4 * v + lg;
-                        if (kk >= r0 && kk < r0 + ni) wr[ups][v] = (double)a.y[i + (kk - r0)];
+                        if (kk >= r0 && kk < r0 + ni) wr[ups][v] = x1[K::X1_YV + (kk - r0)];  // y of block row kk - r0
 #pragma unroll
                         for (int u2 = 0; u2 < NU; ++u2) {
                             const int row = 16 * u2 + 4 * v + lg, colp = 16 * u + li;
@@ -838,8 +873,8 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
                         }
                     }
                 }
-#pragma unroll 1
-                for (int j = 0; j < ni; ++j) trh += x1[K::X1_GG + j];
+#pragma unroll
+                for (int j = 0; j < 16; ++j) trh += j < ni ? x1[K::X1_GG + j] : 0.0;
                 r = r0 + ni;
                 i += ni;
                 applied += ni;
@@ -849,7 +884,7 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
                 }
                 continue;
             }
-            const int ndd = (int)x1[K::X1_COL];
+            const int ndd = __builtin_amdgcn_readfirstlane((int)x1[K::X1_COL]);
 
             // ---- T = Z L^-T (row kk per thread, in place) and dw = T c ----
             if (tl < 16 * nur) {
