@@ -175,12 +175,47 @@ __global__ void __launch_bounds__(NT) k_pinv_track(const double *A, const double
             sK[j] = kj;
         }
         __syncthreads();  // K and beta complete
-        // A^+ <- [A^+ - K beta^T, K]: one wave per row j, lanes over columns.
-        for (int j = wid; j < m; j += NW) {
-            const double kj = sK[j];
-            double *arow = Apb + (size_t)j * n;
-            for (int c = lane; c < i; c += 64) arow[c] -= kj * beta[c];
-            if (lane == 0) arow[i] = kj;
+        // A^+ <- [A^+ - K beta^T, K]: each wave takes four rows j at a time, lanes
+        // over pairs of columns (16-byte accesses, the four rows' loads in flight
+        // together).  Rows start 16-byte aligned when n is even and A^+ is; column
+        // i of the pair that straddles it receives K_j from the same store.
+        if ((n & 1) == 0 && (reinterpret_cast<uintptr_t>(Apb) & 15) == 0) {
+            for (int j0 = wid; j0 < m; j0 += 4 * NW) {
+                double kq[4];
+                double *aq[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int jq = j0 + u * NW;
+                    kq[u] = jq < m ? sK[jq] : 0.0;
+                    aq[u] = Apb + (size_t)(jq < m ? jq : j0) * n;
+                }
+                for (int c = 2 * lane; c < i; c += 128) {
+                    // c + 1 <= i <= n - 1: the pair is inside the row (beta has n entries)
+                    const double2 bt = make_double2(beta[c], beta[c + 1]);
+                    double2 av[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) av[u] = *reinterpret_cast<const double2 *>(aq[u] + c);
+                    const bool last = c + 1 == i;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        av[u].x -= kq[u] * bt.x;
+                        av[u].y = last ? kq[u] : av[u].y - kq[u] * bt.y;
+                        if (j0 + u * NW < m) *reinterpret_cast<double2 *>(aq[u] + c) = av[u];
+                    }
+                }
+                if (lane == 0 && (i & 1) == 0) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (j0 + u * NW < m) aq[u][i] = kq[u];
+                }
+            }
+        } else {
+            for (int j = wid; j < m; j += NW) {
+                const double kj = sK[j];
+                double *arow = Apb + (size_t)j * n;
+                for (int c = lane; c < i; c += 64) arow[c] -= kj * beta[c];
+                if (lane == 0) arow[i] = kj;
+            }
         }
         for (int t = tid; t < m * q; t += NT) Xb[t] += sK[t / q] * sdy[t % q];
         if (indep) {
