@@ -43,7 +43,18 @@
  *    of Section 2.1 as C (the accepted input rows, exact in either element
  *    type) and H^-1 = (C C^T)^-1 in FP64; rg_batch_get_state forms Ct on
  *    request.  The rounding of x then grows like kappa(C)^2 2^-52 rather
- *    than kappa(C) times the state's unit roundoff.
+ *    than kappa(C) times the state's unit roundoff.  FP64 streams project
+ *    each block's rejections a second time, so that their rank decisions
+ *    hold at FP64 tolerances.
+ *  - Placement: FP32 streams take one of rg_class_count() on-chip classes
+ *    (0 .. rg_class_count()-1).  The FP64 stream of a one-stream handle with
+ *    m <= 128 and r_max <= 64 takes the on-chip class rg_class_count()
+ *    (blocked, FP64 state, factored form); FP64 streams of batches run in the
+ *    global-memory kernel, whose explicit Ct keeps the rank decision at FP64
+ *    tolerances for larger kappa(C).  A stream alone in a handle that no
+ *    class holds runs over the whole GPU; other streams run in the
+ *    global-memory kernel.  RG_OPT_GENERIC_KERNEL and the variants of
+ *    Section 2.2 select the global-memory kernel.
  */
 #ifndef RG_H
 #define RG_H
@@ -216,8 +227,10 @@ rg_status rg_batch_rank(rg_handle h, int32_t *r);
 /* Flags (host, B uint32).  Synchronises. */
 rg_status rg_batch_flags(rg_handle h, uint32_t *flags);
 
-/* Kernel class of every stream (host, B int32): 0 .. rg_class_count()-1, or
- * -1 for the global-memory kernel.  Fixed at init; does not synchronise. */
+/* Kernel class of every stream (host, B int32): 0 .. rg_class_count()-1 for
+ * FP32 streams, rg_class_count() for the FP64 stream of a one-stream handle
+ * in the FP64 on-chip class,
+ * or -1 for the global-memory kernel.  Fixed at init; does not synchronise. */
 rg_status rg_batch_classes(rg_handle h, int32_t *cls);
 
 /* Copy stream b's state to caller buffers (device; any may be NULL): C and
@@ -316,11 +329,13 @@ size_t rg_pinv_track_noalloc_max_bytes(void);
 
 /* FP32 streams run in one of rg_class_count() on-chip kernel classes, or in
  * the global-memory kernel.  By default a stream takes the smallest class that
- * holds it; a tuning tool can measure the classes and install rules instead. */
+ * holds it; a tuning tool can measure the classes and install rules instead.
+ * Class rg_class_count() holds FP64 streams only and takes no rules. */
 int32_t rg_class_count(void);
 
-/* Shape of class cls: largest rank capacity, largest m, threads per stream
- * (host outputs, each nullable).  RG_E_INVALID for cls out of range. */
+/* Shape of class cls (0 .. rg_class_count(), the last the FP64 class):
+ * largest rank capacity, largest m, threads per stream (host outputs, each
+ * nullable).  RG_E_INVALID for cls out of range. */
 rg_status rg_class_info(int32_t cls, int32_t *r_max_cap, int32_t *m_cap, int32_t *threads);
 
 /* *fits (host) = 1 if class cls can hold a stream with m regressors and rank

@@ -60,10 +60,15 @@ struct Layout {
 };
 
 // Kernel class of a stream (-1: generic kernel), and whether that class keeps
-// the dual basis in factored form (the blocked on-chip classes do).
-int stream_class(int m, int r_max, int dtype, uint32_t opts) {
+// the dual basis in factored form (the blocked on-chip classes do).  FP64
+// streams of batches stay in the generic kernel, whose explicit Ct holds its
+// rank decisions for kappa(C) beyond the factored form's reach; the stream of
+// a one-stream FP64 handle takes the FP64 class when it fits (it would
+// otherwise run over the whole GPU, also in factored form).
+int stream_class(int32_t B, int m, int r_max, int dtype, uint32_t opts) {
     const bool generic = (opts & (RG_OPT_GENERIC_KERNEL | RG_OPT_ORTHOGONAL | RG_OPT_ORTHONORMAL)) != 0;
-    return generic ? -1 : rg::choose_class(m, r_max, dtype);
+    if (generic || (dtype == RG_F64 && B > 1)) return -1;
+    return rg::choose_class(m, r_max, dtype);
 }
 
 // A handle of one stream that no on-chip class holds runs it over the whole
@@ -84,7 +89,7 @@ Layout plan_layout(int32_t B, const int32_t *m, const int32_t *r_max, size_t esi
         M.ldm = (int32_t)align_up((size_t)M.m, quantum);
         M.r = 0;
         M.flags = 0;
-        M.cls = stream_class(M.m, M.r_max, dtype, opts);
+        M.cls = stream_class(B, M.m, M.r_max, dtype, opts);
         M.h_off = -1;
         if (rg::class_factored(M.cls) || big_stream(B, M.cls, M.m, opts)) {
             M.h_off = (int64_t)L.h_elems;
@@ -142,9 +147,8 @@ rg_status upload_order(rg_ctx *h) {
     }
     HIPCHK(hipMemcpyAsync(h->d_order, order.data(), sizeof(int32_t) * B, hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
-    if (h->dtype == RG_F32)
-        for (int f = 1; f < nfam; ++f)
-            if (h->fam_count[f] > 0) HIPCHK(rg::prepare_class(f - 1, h->fam_rows[f]));
+    for (int f = 1; f < nfam; ++f)
+        if (h->fam_count[f] > 0) HIPCHK(rg::prepare_class(f - 1, h->fam_rows[f]));
     // Forked streams only when two or more class families are active; with one
     // the family runs on the handle's stream.
     int nact = 0;
@@ -302,7 +306,7 @@ const char *rg_status_string(rg_status s) {
 int32_t rg_class_count(void) { return RG_NUM_CLASSES; }
 
 rg_status rg_class_info(int32_t cls, int32_t *r_max_cap, int32_t *m_cap, int32_t *threads) {
-    if (cls < 0 || cls >= RG_NUM_CLASSES) return RG_E_INVALID;
+    if (cls < 0 || cls > RG_CLASS_F64) return RG_E_INVALID;
     if (r_max_cap) *r_max_cap = rg::class_rmax(cls);
     if (m_cap) *m_cap = rg::class_mmax(cls);
     if (threads) *threads = rg::class_threads(cls);
@@ -310,7 +314,7 @@ rg_status rg_class_info(int32_t cls, int32_t *r_max_cap, int32_t *m_cap, int32_t
 }
 
 rg_status rg_class_fits(int32_t cls, int32_t m, int32_t r_max, int32_t *fits) {
-    if (!fits || cls < 0 || cls >= RG_NUM_CLASSES || m <= 0 || r_max <= 0) return RG_E_INVALID;
+    if (!fits || cls < 0 || cls > RG_CLASS_F64 || m <= 0 || r_max <= 0) return RG_E_INVALID;
     *fits = rg::class_fits(cls, m, r_max) ? 1 : 0;
     return RG_OK;
 }

@@ -3,12 +3,14 @@
 #pragma once
 #include "rg_internal.h"
 
-#define RG_NUM_CLASSES 9
-#define RG_MAX_FAMILIES (1 + RG_NUM_CLASSES)  // family 0 = generic global-state kernel
+#define RG_NUM_CLASSES 9                      // classes of FP32 streams: 0 .. 8
+#define RG_CLASS_F64 RG_NUM_CLASSES           // the blocked kernel for FP64 streams
+#define RG_MAX_FAMILIES (2 + RG_NUM_CLASSES)  // family 0 = generic global-state kernel, family c + 1 = class c
 
 namespace rg {
 // Class index for a stream of m regressors and capacity r_max, or -1 when the
-// stream goes to the generic kernel (FP64 state, or too large for the chip).
+// stream goes to the generic kernel (too large for the chip).  FP64 streams
+// (dtype 1) take RG_CLASS_F64 when it holds them.
 int choose_class(int m, int r_max, int dtype);
 int class_rmax(int cls);
 // Whether class cls keeps the dual basis in factored form (Ct = H^-1 C, with
@@ -21,8 +23,9 @@ hipError_t prepare_class(int cls, int rows_alloc);
 // r_max among them (rows of Ct reserved in LDS).
 template <typename T>
 hipError_t launch_push_class(int cls, const PushArgs<T> &a, int rows_alloc, hipStream_t s);
-// Whether class cls can hold a stream of m regressors and capacity r_max,
-// and the class's shape (rank capacity, column capacity, threads).
+// Whether class cls can hold a stream of m regressors and capacity r_max (by
+// shape; RG_CLASS_F64 takes FP64 streams only, the others FP32 streams), and
+// the class's shape (rank capacity, column capacity, threads).
 bool class_fits(int cls, int m, int r_max);
 int class_mmax(int cls);
 int class_threads(int cls);
@@ -36,4 +39,11 @@ int mf_threads(int v);
 int mf_rmax(int v);
 hipError_t mf_prepare(int v, int r_max);
 hipError_t mf_launch(int v, const PushArgs<float> &a, int r_max, hipStream_t s);
+// Its FP64 variant (class RG_CLASS_F64).
+bool mf64_fits(int m, int r_max);
+int mf64_rmax();
+int mf64_mmax();
+int mf64_threads();
+hipError_t mf64_prepare(int r_max);
+hipError_t mf64_launch(const PushArgs<double> &a, int r_max, hipStream_t s);
 }  // namespace rg

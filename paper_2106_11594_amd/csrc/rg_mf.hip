@@ -16,9 +16,10 @@
 //
 // One workgroup of NW waves (4 or 8) owns one stream for a whole push.  Lane
 // l of wave w has i = l & 15 and g = l >> 4.  Residency:
-//   C     LDS, FP32, row-major, leading dimension MMAX.  Logical float4 chunk
-//         c of row k sits at physical chunk c ^ (k & 15), so that the 16 rows
-//         a matrix-core operand touches fall into different banks;
+//   C     LDS, in the element type of the stream (FP32; FP64 in the FP64
+//         variant), row-major, leading dimension MMAX.  Logical chunk of four
+//         elements c of row k sits at physical chunk c ^ (k & 15), so that the
+//         16 rows a matrix-core operand touches fall into different banks;
 //   P^-1, H^-1  registers, FP64, 16 x 16 output tiles (u', u) for the column
 //         tiles u = w + NW ups of this wave:
 //         p[u'][ups][v] = P^-1[16u' + 4v + g][16u + i], h likewise;
@@ -70,6 +71,9 @@ __device__ inline d4 mma(double a, double b, d4 c) {
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
+// Independent runs: a Gram pivot below this fraction of its diagonal ends the run.
+constexpr double PIV_AMBIG = 1e-4;
+
 // 1/sqrt(x) in FP64: the hardware estimate refined by two Newton steps
 // y <- y (3 - x y^2) / 2, each of which doubles the number of correct bits.
 __device__ inline double rsqrt_f64(double x) {
@@ -80,9 +84,11 @@ __device__ inline double rsqrt_f64(double x) {
     return y;
 }
 
-template <int RMAX_, int MMAX_, int NW_>
+template <int RMAX_, int MMAX_, int NW_, typename E_ = float>
 struct MF {
     static constexpr int RMAX = RMAX_, MMAX = MMAX_, NW = NW_;
+    using E = E_;                                 // element type of C and of the rows (FP32 or FP64)
+    static constexpr int EW = sizeof(E) / 4;      // 32-bit words per element
     static_assert((RMAX == 64 || RMAX == 128) && (RMAX / 16) % NW == 0, "whole row tiles per wave");
     static_assert(MMAX % 64 == 0 && MMAX <= 256 && (NW == 4 || NW == 8), "4 or 8 waves");
     static constexpr int NT = 64 * NW;
@@ -92,7 +98,7 @@ struct MF {
     static constexpr int RS = 4 * NW;                                 // row stride of a thread in row mode
     static constexpr int NB = RMAX / RS;                              // C rows per thread in row mode
     static constexpr int KB = 16;                                     // rows per block
-    static constexpr int CH = MMAX / 4;                               // float4 chunks per row
+    static constexpr int CH = MMAX / 4;                               // chunks of 4 elements per row
     // X1 (doubles): block-mode scalars and partial sums, or the row-mode vectors
     static constexpr int X1_RR = 0, X1_GW = 16 * NW, X1_GG = 32 * NW, X1_YV = 32 * NW + 16;
     // S partials: 4 records of 16 x 16 with row stride 17, so that reading one row per lane is free of bank conflicts
@@ -100,7 +106,7 @@ struct MF {
     static constexpr int X1_SP = 32 * NW + 64, X1_L = X1_SP + 4 * SPS, X1_C = X1_L + 256, X1_COL = X1_C + 32;
     // Waves per SIMD the register allocation is held to: two for the 4-wave
     // variants whose LDS footprint lets two workgroups share a CU (m <= 192)
-    static constexpr int OCC = (NW == 4 && MMAX <= 192) ? 2 : 1;
+    static constexpr int OCC = (NW == 4 && MMAX <= 192 && EW == 1) ? 2 : 1;
     // HG: H^-1 stays in the stream's state in global memory (L2-resident) instead of
     // registers, where P^-1 and H^-1 together would not fit (RMAX = 128).  It is
     // only read by dependent rows, and each lane reads and writes its own tile
@@ -116,10 +122,36 @@ struct MF {
     // row mode: gamma, zeta, v = C Gamma, the reduction records, Gamma_r (three separate
     // vectors, so that no row writes one that a wave may still read for the row before)
     static constexpr int X1_GAM = 0, X1_ZETA = RMAX, X1_V = 2 * RMAX, X1_RED = 3 * RMAX, X1_GR = 3 * RMAX + 4 * NW;
-    static constexpr int X1_D = cmax(cmax(KB * MMAX / 2, X1_DW + RMAX), X1_GR + MMAX);
+    static constexpr int X1_D = cmax(cmax(KB * MMAX * EW / 2, X1_DW + RMAX), X1_GR + MMAX);
     // X2 (doubles): V and G (16 x RMAX), then Z, T or U (RMAX x 16); or the row ring
-    static constexpr int X2_D = cmax(KB * RMAX, 3 * MMAX / 2);
+    static constexpr int X2_D = cmax(KB * RMAX, 3 * MMAX * EW / 2);
+    // X3 (doubles, FP64 variant only): the rejections R (16 x MMAX, swizzled like
+    // the block rows) and V2 = R C^T, then G2 = V2 H^-1 (16 x RMAX), for the
+    // second projection of a block's rejections
+    static constexpr int X3_D = EW == 2 ? 16 * MMAX + 16 * RMAX : 0;
 };
+
+// Chunks of four elements: float4 for FP32 streams, double4 for FP64 streams.
+template <typename T>
+struct V4T;
+template <>
+struct V4T<float> {
+    typedef float4 type;
+};
+template <>
+struct V4T<double> {
+    typedef double4 type;
+};
+template <typename T>
+__device__ inline typename V4T<T>::type mk4(T a, T b, T c, T d);
+template <>
+__device__ inline float4 mk4<float>(float a, float b, float c, float d) {
+    return make_float4(a, b, c, d);
+}
+template <>
+__device__ inline double4 mk4<double>(double a, double b, double c, double d) {
+    return make_double4(a, b, c, d);
+}
 
 // Swizzled positions of G[j][kk] (16 x RMAX) and of Z, T, U [kk][j] (RMAX x 16).
 template <int RMAX>
@@ -154,14 +186,16 @@ __device__ inline void block_sum4(double &a, double &b, double &c, double &d, do
 // One stream's push by the whole workgroup (every thread calls it with the same
 // b_id and returns at the same point).
 template <class K>
-__device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, int b_id, double *smem) {
+__device__ __forceinline__ void push_stream(const PushArgs<typename K::E> &a, int ra, int b_id, double *smem) {
+    using E = typename K::E;
+    using V4 = typename V4T<E>::type;
     constexpr int RMAX = K::RMAX, MMAX = K::MMAX, NU = K::NU, UPW = K::UPW, TPW = K::TPW;
     constexpr int NB = K::NB, KB = K::KB, CH = K::CH, NW = K::NW, NTT = K::NTT, RS = K::RS;
-    float *sct = reinterpret_cast<float *>(smem);  // C: ra x MMAX (ra: multiple of 16)
-    double *x1 = smem + (size_t)ra * MMAX / 2;
+    E *sct = reinterpret_cast<E *>(smem);  // C: ra x MMAX (ra: multiple of 16)
+    double *x1 = smem + (size_t)ra * MMAX * K::EW / 2;
     double *x2 = x1 + K::X1_D;
-    float *x1f = reinterpret_cast<float *>(x1);   // block rows, 16 x MMAX, swizzled like C
-    float *ring = reinterpret_cast<float *>(x2);  // row mode: 3 rows of MMAX
+    E *x1f = reinterpret_cast<E *>(x1);   // block rows, 16 x MMAX, swizzled like C
+    E *ring = reinterpret_cast<E *>(x2);  // row mode: 3 rows of MMAX
 
     // the wave index is uniform over the wave: held in a scalar register, so that
     // branches and addresses that depend only on it are scalar
@@ -170,7 +204,7 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
     const int m = M->m, rmax = M->r_max, ldm = M->ldm;
     int r = M->r;
     uint32_t flags = M->flags;
-    float *Cg = a.state + M->state_off;
+    E *Cg = a.state + M->state_off;
     double *Pg = a.preg + M->p_off;
     double *Hg = a.hreg + M->h_off;
     double *wg = a.wreg + M->w_off;
@@ -185,7 +219,7 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
         goff = 0;
     }
     if (flags != 0u || i0 >= i1) return;  // whole workgroup: nothing to do
-    const float *G0 = a.gamma + goff;     // row i starts at G0 + (i - i0) * m
+    const E *G0 = a.gamma + goff;     // row i starts at G0 + (i - i0) * m
     const int cba4 = (m + 63) / 64;       // 64-column groups (row mode)
     const int nq = (m + 15) / 16;         // 16-column chunks (block mode)
 
@@ -193,18 +227,18 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
     double trh = 0.0;  // trace(C C^T) = sum of the squared norms of the rows of C
     for (int idx = t; idx < ra * CH; idx += K::NT) {
         const int k = idx / CH, c = idx - k * CH;
-        float v[4];
+        E v[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int j = 4 * c + e;
             v[e] = (k < r && j < m) ? Cg[(size_t)k * ldm + j] : 0.0f;
             trh += (double)v[e] * (double)v[e];
         }
-        *reinterpret_cast<float4 *>(sct + (size_t)k * MMAX + 4 * (c ^ (k & 15))) = make_float4(v[0], v[1], v[2], v[3]);
+        *reinterpret_cast<V4 *>(sct + (size_t)k * MMAX + 4 * (c ^ (k & 15))) = mk4<E>(v[0], v[1], v[2], v[3]);
     }
     {
         double z0 = 0.0, z1 = 0.0, z2 = 0.0;
-        block_sum4<NW>(trh, z0, z1, z2, smem + (size_t)ra * MMAX / 2 + K::X1_RED);
+        block_sum4<NW>(trh, z0, z1, z2, x1 + K::X1_RED);
     }
     const int li = lane & 15, lg = lane >> 4;
     constexpr int NUH = K::HG ? 1 : NU, UPWH = K::HG ? 1 : UPW;
@@ -279,24 +313,24 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
     __syncthreads();
 
     // Block rows come through registers: pfv holds rows pf_i .. pf_i + 15 as
-    // float4 chunks (thread tl has chunks tl + NT e), pfy the target of row
+    // chunks of four elements (thread tl has chunks tl + NT e), pfy the target of row
     // pf_i + (lane & 15).
     constexpr int PFB = (KB * CH + K::NT - 1) / K::NT;
-    float4 pfv[PFB];
-    float pfy = 0.0f;
+    V4 pfv[PFB];
+    E pfy = 0;
     int64_t pf_i = -1;
-    auto fetch_block = [&](const float *src0, const float *ysrc, int nrows, int mm, int tid, float4 (&dst)[PFB], float &ydst) {
+    auto fetch_block = [&](const E *src0, const E *ysrc, int nrows, int mm, int tid, V4 (&dst)[PFB], E &ydst) {
 #pragma unroll
         for (int e = 0; e < PFB; ++e) {
             const int idx = tid + K::NT * e, j = idx / CH, cc = idx - j * CH;
-            const float *src = src0 + (int64_t)j * mm;
-            float v[4];
+            const E *src = src0 + (int64_t)j * mm;
+            E v[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int col = 4 * cc + q;
                 v[q] = (idx < KB * CH && j < nrows && col < mm) ? src[col] : 0.0f;
             }
-            dst[e] = make_float4(v[0], v[1], v[2], v[3]);
+            dst[e] = mk4<E>(v[0], v[1], v[2], v[3]);
         }
         ydst = (tid & 15) < nrows ? ysrc[tid & 15] : 0.0f;
     };
@@ -307,8 +341,8 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
     bool ring_ok = false;  // row mode: row i is in ring slot cur, pre holds row i + 1
     int cur = 0;
     constexpr int PF = (MMAX + K::NT - 1) / K::NT;
-    float pre[PF];
-    float y_next = 0.0f;
+    E pre[PF];
+    E y_next = 0;
 
     while (i < i1) {
         // Lane indices are re-derived from an opaque copy of the lane id in every
@@ -333,7 +367,7 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
 #pragma unroll
             for (int e = 0; e < PFB; ++e) {
                 const int idx = tl + K::NT * e, j = idx / CH, cc = idx - j * CH;
-                if (idx < KB * CH) *reinterpret_cast<float4 *>(x1f + j * MMAX + 4 * (cc ^ j)) = pfv[e];
+                if (idx < KB * CH) *reinterpret_cast<V4 *>(x1f + j * MMAX + 4 * (cc ^ j)) = pfv[e];
             }
             const double yrow = (double)pfy;
             __syncthreads();
@@ -351,28 +385,28 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
                 for (int ups = 0; ups < UPW; ++ups) gacc[ups] = gacc2[ups] = (d4){0.0, 0.0, 0.0, 0.0};
                 // chunk 4q + g of a row with (row & 15) == i sits at physical chunk (4q + g) ^ i;
                 // the operands of chunk q + 1 are loaded while chunk q is multiplied
-                const float *gbase = x1f + li * MMAX;
-                const float *cbase[UPW];
+                const E *gbase = x1f + li * MMAX;
+                const E *cbase[UPW];
 #pragma unroll
                 for (int ups = 0; ups < UPW; ++ups) cbase[ups] = sct + (size_t)(16 * (wv + NW * ups) + li) * MMAX;
-                float4 gb = *reinterpret_cast<const float4 *>(gbase + 4 * (lg ^ li));
-                float4 ca[UPW];
+                V4 gb = *reinterpret_cast<const V4 *>(gbase + 4 * (lg ^ li));
+                V4 ca[UPW];
 #pragma unroll
                 for (int ups = 0; ups < UPW; ++ups)
-                    ca[ups] = wv + NW * ups < nur ? *reinterpret_cast<const float4 *>(cbase[ups] + 4 * (lg ^ li))
-                                                  : make_float4(0.f, 0.f, 0.f, 0.f);
+                    ca[ups] = wv + NW * ups < nur ? *reinterpret_cast<const V4 *>(cbase[ups] + 4 * (lg ^ li))
+                                                  : mk4<E>(0, 0, 0, 0);
 #pragma unroll 1
                 for (int q = 0; q < nq; ++q) {
-                    const float4 gq = gb;
-                    float4 cq[UPW];
+                    const V4 gq = gb;
+                    V4 cq[UPW];
 #pragma unroll
                     for (int ups = 0; ups < UPW; ++ups) cq[ups] = ca[ups];
                     if (q + 1 < nq) {
                         const int phn = (4 * q + 4 + lg) ^ li;
-                        gb = *reinterpret_cast<const float4 *>(gbase + 4 * phn);
+                        gb = *reinterpret_cast<const V4 *>(gbase + 4 * phn);
 #pragma unroll
                         for (int ups = 0; ups < UPW; ++ups)
-                            if (wv + NW * ups < nur) ca[ups] = *reinterpret_cast<const float4 *>(cbase[ups] + 4 * phn);
+                            if (wv + NW * ups < nur) ca[ups] = *reinterpret_cast<const V4 *>(cbase[ups] + 4 * phn);
                     }
                     const double b0 = gq.x, b1 = gq.y, b2 = gq.z, b3 = gq.w;
                     if ((q & (NW - 1)) == wv) gsq += b0 * b0 + b1 * b1 + b2 * b2 + b3 * b3;  // this wave's share
@@ -519,35 +553,167 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
             // ---- R^T = Gamma_blk^T - C^T G^T, ||R_i||^2 and this wave's part of R R^T ----
             double rsq = 0.0;
             d4 sacc_r = (d4){0.0, 0.0, 0.0, 0.0};
+            if constexpr (K::EW == 1) {
 #pragma unroll
-            for (int tau = 0; tau < TPW; ++tau) {
-                const int ct = wv + NW * tau;
-                if (ct < nq && !skip_r) {
-                    d4 d = (d4){gi[tau][0], gi[tau][1], gi[tau][2], gi[tau][3]};
-                    if constexpr (K::HG) {
+                for (int tau = 0; tau < TPW; ++tau) {
+                    const int ct = wv + NW * tau;
+                    if (ct < nq && !skip_r) {
+                        d4 d = (d4){gi[tau][0], gi[tau][1], gi[tau][2], gi[tau][3]};
+                        if constexpr (K::HG) {
 #pragma unroll 1
-                        for (int u2 = 0; u2 < nur; ++u2) {
+                            for (int u2 = 0; u2 < nur; ++u2) {
 #pragma unroll
-                            for (int v = 0; v < 4; ++v) {
-                                const int s = 4 * u2 + v;
-                                d = mma(cval(s, ct), -x2[gpos<RMAX>(li, 4 * s + lg)], d);
+                                for (int v = 0; v < 4; ++v) {
+                                    const int s = 4 * u2 + v;
+                                    d = mma(cval(s, ct), -x2[gpos<RMAX>(li, 4 * s + lg)], d);
+                                }
+                            }
+                        } else {
+#pragma unroll
+                        for (int u2 = 0; u2 < NU; ++u2) {
+                            if (u2 < nur) {
+#pragma unroll
+                                for (int v = 0; v < 4; ++v) {
+                                    const int s = 4 * u2 + v;
+                                    d = mma(cval(s, ct), -x2[gpos<RMAX>(li, 4 * s + lg)], d);
+                                }
                             }
                         }
-                    } else {
+                        }
+                        rsq += d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + d[3] * d[3];
 #pragma unroll
-                    for (int u2 = 0; u2 < NU; ++u2) {
-                        if (u2 < nur) {
+                        for (int v = 0; v < 4; ++v) sacc_r = mma(d[v], d[v], sacc_r);
+                    }
+                }
+            } else {
+                // FP64 streams: the projections carry kappa(C)^2 2^-52 relative error
+                // through H^-1, more than a small eps tolerates, so the rejections are
+                // projected a second time (as in classical Gram-Schmidt with
+                // reorthogonalisation): G2 = (R C^T) H^-1, R <- R - G2 C and G <- G + G2,
+                // the refined coordinates of the block rows.
+                static_assert(!K::HG, "H^-1 in registers");
+                d4 dt[TPW];
+#pragma unroll
+                for (int tau = 0; tau < TPW; ++tau) {
+                    const int ct = wv + NW * tau;
+                    dt[tau] = (d4){0.0, 0.0, 0.0, 0.0};
+                    if (ct < nq && !skip_r) {
+                        d4 d = (d4){gi[tau][0], gi[tau][1], gi[tau][2], gi[tau][3]};
+#pragma unroll
+                        for (int u2 = 0; u2 < NU; ++u2) {
+                            if (u2 < nur) {
+#pragma unroll
+                                for (int v = 0; v < 4; ++v) {
+                                    const int s = 4 * u2 + v;
+                                    d = mma(cval(s, ct), -x2[gpos<RMAX>(li, 4 * s + lg)], d);
+                                }
+                            }
+                        }
+                        dt[tau] = d;
+                    }
+                }
+                if (!skip_r) {
+                    double *xr = x2 + K::X2_D, *xv = xr + 16 * MMAX;
+                    // R to X3, row i with chunk c at c ^ i (like the block rows)
+#pragma unroll
+                    for (int tau = 0; tau < TPW; ++tau) {
+                        const int ct = wv + NW * tau;
+                        if (ct < nq) {
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) xr[li * MMAX + 4 * ((4 * ct + v) ^ li) + lg] = dt[tau][v];
+                        }
+                    }
+                    __syncthreads();
+                    // V2 = R C^T on this wave's row tiles
+#pragma unroll
+                    for (int ups = 0; ups < UPW; ++ups) {
+                        const int u = wv + NW * ups;
+                        if (u < nur) {
+                            d4 va = (d4){0.0, 0.0, 0.0, 0.0}, vb = va;
+#pragma unroll 1
+                            for (int q = 0; q < nq; ++q) {
+                                const int ph = (4 * q + lg) ^ li;
+                                const V4 rv = *reinterpret_cast<const V4 *>(xr + li * MMAX + 4 * ph);
+                                const V4 cv = *reinterpret_cast<const V4 *>(sct + (size_t)(16 * u + li) * MMAX + 4 * ph);
+                                va = mma(cv.x, rv.x, va);
+                                vb = mma(cv.y, rv.y, vb);
+                                va = mma(cv.z, rv.z, va);
+                                vb = mma(cv.w, rv.w, vb);
+                            }
+                            va += vb;
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) xv[gpos<RMAX>(li, 16 * u + 4 * v + lg)] = va[v];
+                        }
+                    }
+                    __syncthreads();
+                    // G2 = V2 H^-1 on this wave's row tiles, and its part of G2 w
+                    d4 g2[UPW];
+                    double g2w = 0.0;
+#pragma unroll
+                    for (int ups = 0; ups < UPW; ++ups) {
+                        const int u = wv + NW * ups;
+                        g2[ups] = (d4){0.0, 0.0, 0.0, 0.0};
+                        if (u < nur) {
+                            d4 gb2 = (d4){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                            for (int u2 = 0; u2 < NU; ++u2) {
+                                if (u2 < nur) {
+                                    const d4 ht = hload(u2, ups, r);
+#pragma unroll
+                                    for (int v = 0; v < 4; v += 2) {
+                                        g2[ups] = mma(ht[v], xv[gpos<RMAX>(li, 16 * u2 + 4 * v + lg)], g2[ups]);
+                                        gb2 = mma(ht[v + 1], xv[gpos<RMAX>(li, 16 * u2 + 4 * v + 4 + lg)], gb2);
+                                    }
+                                }
+                            }
+                            g2[ups] += gb2;
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) g2w += g2[ups][v] * wr[ups][v];
+                        }
+                    }
+                    gwp += sum_rows(g2w);
+                    __syncthreads();  // every read of V2 is done
+#pragma unroll
+                    for (int ups = 0; ups < UPW; ++ups) {
+                        const int u = wv + NW * ups;
+                        if (u < nur) {
 #pragma unroll
                             for (int v = 0; v < 4; ++v) {
-                                const int s = 4 * u2 + v;
-                                d = mma(cval(s, ct), -x2[gpos<RMAX>(li, 4 * s + lg)], d);
+                                xv[gpos<RMAX>(li, 16 * u + 4 * v + lg)] = g2[ups][v];
+                                x2[gpos<RMAX>(li, 16 * u + 4 * v + lg)] += g2[ups][v];
                             }
                         }
                     }
-                    }
-                    rsq += d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + d[3] * d[3];
+                    __syncthreads();
+                    // R <- R - (G2 C)^T
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) sacc_r = mma(d[v], d[v], sacc_r);
+                    for (int tau = 0; tau < TPW; ++tau) {
+                        const int ct = wv + NW * tau;
+                        if (ct < nq) {
+                            d4 d = dt[tau];
+#pragma unroll
+                            for (int u2 = 0; u2 < NU; ++u2) {
+                                if (u2 < nur) {
+#pragma unroll
+                                    for (int v = 0; v < 4; ++v) {
+                                        const int s = 4 * u2 + v;
+                                        d = mma(cval(s, ct), -xv[gpos<RMAX>(li, 4 * s + lg)], d);
+                                    }
+                                }
+                            }
+                            dt[tau] = d;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int tau = 0; tau < TPW; ++tau) {
+                    const int ct = wv + NW * tau;
+                    if (ct < nq && !skip_r) {
+                        const d4 d = dt[tau];
+                        rsq += d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + d[3] * d[3];
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) sacc_r = mma(d[v], d[v], sacc_r);
+                    }
                 }
             }
             rsq = sum_rows(rsq);
@@ -567,6 +733,7 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
             int nd;
             uint32_t stop = 0u;
             double g2row;  // ||Gamma_i||^2 of block row i
+            double r2row;  // ||R_i||^2: its rejection against the span of C
             bool badrow;   // block row i or its target is not finite
             {
                 double r2 = 0.0;
@@ -575,6 +742,7 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
                 const double g2 = x1[K::X1_GG + li], yj = x1[K::X1_YV + li];
                 const bool bad = li < nblk && (!isfinite(g2) || !isfinite(yj));
                 g2row = g2;
+                r2row = r2;
                 badrow = bad;
                 const double nr = sqrt(r2);
                 const bool indep = li < nblk && !((r2 == 0.0) || (nr < eps) || (nr < eps * sqrt(g2)));
@@ -723,9 +891,14 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
                     // finite rows that pass it and fit below the rank capacity.
                     const double epsl = a.eps >= 0.0 ? a.eps
                                                      : ((double)m * m * (r0 + li) + (double)m * (r0 + li) + (double)m) * 0x1p-52;
+                    // A pivot below PIV_AMBIG of the row's squared rejection against C
+                    // carries the rounding of that subtraction at a relative size that
+                    // a small eps (FP64 streams) cannot resolve: the run ends before
+                    // the row, which the next block tests with its explicit rejection
+                    // against the grown C (its own pivot there is its diagonal).
                     const double nrm = sqrt(mypiv);
                     const bool ok = li < nst && !badrow && mypiv > 0.0 && isfinite(mypiv) && !(nrm < epsl) &&
-                                    !(nrm < epsl * sqrt(g2row));
+                                    !(nrm < epsl * sqrt(g2row)) && mypiv >= PIV_AMBIG * r2row;
                     const uint64_t failm = __ballot(!ok) & 0xFFFFull;
                     const uint64_t badm = __ballot(li < nblk && badrow) & 0xFFFFull;
                     const int ni = failm ? (int)__builtin_ctzll(failm) : 16;
@@ -808,18 +981,18 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
                 // rows r0 .. r0 + ni - 1 of C: the raw block rows
                 for (int idx = t; idx < ni * CH; idx += K::NT) {
                     const int j = idx / CH, cc = idx - j * CH, k = r0 + j;
-                    const float *src = G0 + (i - i0 + j) * (int64_t)m;
-                    float v[4];
+                    const E *src = G0 + (i - i0 + j) * (int64_t)m;
+                    E v[4];
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         // unconditional loads (column 0 past m), all in flight together
                         int col = 4 * cc + e < m ? 4 * cc + e : 0;
                         asm("" : "+v"(col));
-                        const float x = src[col];
+                        const E x = src[col];
                         v[e] = 4 * cc + e < m ? x : 0.0f;
                     }
-                    *reinterpret_cast<float4 *>(sct + (size_t)k * MMAX + 4 * (cc ^ (k & 15))) =
-                        make_float4(v[0], v[1], v[2], v[3]);
+                    *reinterpret_cast<V4 *>(sct + (size_t)k * MMAX + 4 * (cc ^ (k & 15))) =
+                        mk4<E>(v[0], v[1], v[2], v[3]);
                 }
                 __syncthreads();
 #pragma unroll
@@ -952,16 +1125,16 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
         }
 
         // ================= one row (Algorithm 1) =================
-        float *sg_ring = ring;
+        E *sg_ring = ring;
         if (!ring_ok) {
             __syncthreads();  // X2 may still be read by a block step
-            const float *Gi = G0 + (i - i0) * (int64_t)m;
+            const E *Gi = G0 + (i - i0) * (int64_t)m;
 #pragma unroll
             for (int e = 0; e < PF; ++e) {
                 const int j = tl + K::NT * e;
                 if (j < MMAX) sg_ring[cur * MMAX + j] = j < m ? Gi[j] : 0.0f;
             }
-            const float *Gn = Gi + m;
+            const E *Gn = Gi + m;
 #pragma unroll
             for (int e = 0; e < PF; ++e) {
                 const int j = tl + K::NT * e;
@@ -982,7 +1155,7 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
             }
         }
         if (i + 2 < i1) {
-            const float *Gn = G0 + (i + 2 - i0) * (int64_t)m;
+            const E *Gn = G0 + (i + 2 - i0) * (int64_t)m;
 #pragma unroll
             for (int e = 0; e < PF; ++e) {
                 const int j = tl + K::NT * e;
@@ -991,7 +1164,7 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
         }
         const double yv = (double)y_next;
         if (i + 1 < i1) y_next = a.y[i + 1];
-        const float *gcur = sg_ring + cur * MMAX;
+        const E *gcur = sg_ring + cur * MMAX;
         double *sgam = x1 + K::X1_GAM, *szeta = x1 + K::X1_ZETA, *sv = x1 + K::X1_V;
         double *sred = x1 + K::X1_RED, *sgr = x1 + K::X1_GR;
 
@@ -1002,13 +1175,13 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
 #pragma unroll 1
         for (int c4 = 0; c4 < cba4; ++c4) {
             const int ph = 16 * c4 + pj, lc = ph ^ pk15;  // physical chunk of C rows k (k & 15 == pk & 15), logical chunk
-            const float4 gv = *reinterpret_cast<const float4 *>(gcur + 4 * lc);
+            const V4 gv = *reinterpret_cast<const V4 *>(gcur + 4 * lc);
             const double g0 = gv.x, g1 = gv.y, g2v = gv.z, g3 = gv.w;
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
                 const int k = pk + RS * b;
-                float4 v = *reinterpret_cast<const float4 *>(sct + (size_t)min(k, ra - 1) * MMAX + 4 * ph);
-                if (k >= ra) v = make_float4(0.f, 0.f, 0.f, 0.f);
+                V4 v = *reinterpret_cast<const V4 *>(sct + (size_t)min(k, ra - 1) * MMAX + 4 * ph);
+                if (k >= ra) v = mk4<E>(0, 0, 0, 0);
                 gam[b] += (double)v.x * g0;
                 gam[b] += (double)v.y * g1;
                 gam[b] += (double)v.z * g2v;
@@ -1162,8 +1335,8 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
             }
             // append: row r of C (the raw row), P^-1[r][r] = 1, w[r] = y
             if (tl < CH) {
-                const float4 gv = *reinterpret_cast<const float4 *>(gcur + 4 * tl);
-                *reinterpret_cast<float4 *>(sct + (size_t)r * MMAX + 4 * (tl ^ (r & 15))) = gv;
+                const V4 gv = *reinterpret_cast<const V4 *>(gcur + 4 * tl);
+                *reinterpret_cast<V4 *>(sct + (size_t)r * MMAX + 4 * (tl ^ (r & 15))) = gv;
             }
 #pragma unroll
             for (int ups = 0; ups < UPW; ++ups) {
@@ -1199,8 +1372,8 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
     for (int idx = t; idx < ra * CH; idx += K::NT) {
         const int k = idx / CH, cc = idx - k * CH;
         if (k < r) {
-            const float4 v = *reinterpret_cast<const float4 *>(sct + (size_t)k * MMAX + 4 * (cc ^ (k & 15)));
-            const float vv[4] = {v.x, v.y, v.z, v.w};
+            const V4 v = *reinterpret_cast<const V4 *>(sct + (size_t)k * MMAX + 4 * (cc ^ (k & 15)));
+            const E vv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
             for (int e = 0; e < 4; ++e)
                 if (4 * cc + e < m) Cg[(size_t)k * ldm_w + 4 * cc + e] = vv[e];
@@ -1242,13 +1415,13 @@ __device__ __forceinline__ void push_stream(const PushArgs<float> &a, int ra, in
 // barrier after the last stream's stores keeps that read and the previous
 // stream's thread-0 stores in separate barrier intervals.
 template <class K>
-__global__ void __launch_bounds__(K::NT, K::OCC) k_push_mf(PushArgs<float> a, int ra) {
+__global__ void __launch_bounds__(K::NT, K::OCC) k_push_mf(PushArgs<typename K::E> a, int ra) {
     extern __shared__ double smem[];
     if (!a.persistent) {
         push_stream<K>(a, ra, a.order[blockIdx.x], smem);
         return;
     }
-    int *slot = reinterpret_cast<int *>(smem + (size_t)ra * K::MMAX / 2);  // first word of X1
+    int *slot = reinterpret_cast<int *>(smem + (size_t)ra * K::MMAX * K::EW / 2);  // first word of X1
     for (;;) {
         if (threadIdx.x == 0) *slot = (int)atomicAdd(a.counter, 1u);
         __syncthreads();
@@ -1261,7 +1434,7 @@ __global__ void __launch_bounds__(K::NT, K::OCC) k_push_mf(PushArgs<float> a, in
 
 template <class K>
 size_t lds_bytes(int ra) {
-    return sizeof(float) * (size_t)ra * K::MMAX + sizeof(double) * (size_t)(K::X1_D + K::X2_D);
+    return sizeof(typename K::E) * (size_t)ra * K::MMAX + sizeof(double) * (size_t)(K::X1_D + K::X2_D + K::X3_D);
 }
 
 // Rows of Ct reserved in LDS: r_max rounded up to whole 16-row tiles.
@@ -1273,6 +1446,9 @@ using F2 = MF<64, 192, 4>;
 using F3 = MF<128, 192, 8>;
 using F4 = MF<64, 256, 4>;
 using F5 = MF<128, 256, 8>;
+// FP64 streams: C and the rows in FP64 (the variant of FP64 single streams such
+// as m = 64, r = 16 and of small FP64 batches)
+using D0 = MF<64, 128, 4, double>;
 
 template <class K>
 bool fits_k(int m, int r_max) {
@@ -1298,7 +1474,7 @@ template <class K>
 hipError_t prepare_k(int r_max) {
     const int ra = rows16(r_max);
     if (lds_bytes<K>(ra) > 160 * 1024) return hipErrorInvalidValue;
-    static_assert(sizeof(float) * K::RMAX * K::MMAX + sizeof(double) * (K::X1_D + K::X2_D) <= 160 * 1024,
+    static_assert(sizeof(typename K::E) * K::RMAX * K::MMAX + sizeof(double) * (K::X1_D + K::X2_D + K::X3_D) <= 160 * 1024,
                   "every variant fits the LDS at its full capacity");
     static const hipError_t once = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_push_mf<K>),
                                                        hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1314,7 +1490,7 @@ hipError_t prepare_k(int r_max) {
     return hipSuccess;
 }
 template <class K>
-hipError_t launch_k(const PushArgs<float> &a, int r_max, hipStream_t s) {
+hipError_t launch_k(const PushArgs<typename K::E> &a, int r_max, hipStream_t s) {
     const int ra = rows16(r_max);
     const size_t lds = lds_bytes<K>(ra);
     if (lds > 160 * 1024 || ra > K::RMAX) return hipErrorInvalidValue;
@@ -1400,6 +1576,13 @@ hipError_t mf_prepare(int v, int r_max) {
     }
     return hipErrorInvalidValue;
 }
+
+bool mf64_fits(int m, int r_max) { return fits_k<D0>(m, r_max); }
+int mf64_rmax() { return D0::RMAX; }
+int mf64_mmax() { return D0::MMAX; }
+int mf64_threads() { return D0::NT; }
+hipError_t mf64_prepare(int r_max) { return prepare_k<D0>(r_max); }
+hipError_t mf64_launch(const PushArgs<double> &a, int r_max, hipStream_t s) { return launch_k<D0>(a, r_max, s); }
 
 hipError_t mf_launch(int v, const PushArgs<float> &a, int r_max, hipStream_t s) {
     switch (v) {

@@ -511,23 +511,26 @@ hipError_t launch(const PushArgs<float> &a, int rows_alloc, hipStream_t s) {
 
 }  // namespace
 
-// Classes 0..2 are this file's kernel, 3..8 the blocked kernel's variants 0..5.
+// Classes 0..2 are this file's kernel, 3..8 the blocked kernel's variants 0..5,
+// RG_CLASS_F64 the blocked kernel's FP64 variant.
 int class_rmax(int cls) {
     switch (cls) {
         case 0: return C0::RMAX;
         case 1: return C1::RMAX;
         case 2: return C2::RMAX;
+        case RG_CLASS_F64: return mf64_rmax();
     }
     return cls >= 3 ? mf_rmax(cls - 3) : 0;
 }
 
-bool class_factored(int cls) { return cls >= 3 && cls < RG_NUM_CLASSES; }
+bool class_factored(int cls) { return cls >= 3 && cls <= RG_CLASS_F64; }
 
 bool class_fits(int cls, int m, int r_max) {
     switch (cls) {
         case 0: return fits<C0>(m, r_max);
         case 1: return fits<C1>(m, r_max);
         case 2: return fits<C2>(m, r_max);
+        case RG_CLASS_F64: return mf64_fits(m, r_max);
     }
     return cls >= 3 && cls < RG_NUM_CLASSES && mf_fits(cls - 3, m, r_max);
 }
@@ -537,6 +540,7 @@ int class_mmax(int cls) {
         case 0: return C0::MMAX;
         case 1: return C1::MMAX;
         case 2: return C2::MMAX;
+        case RG_CLASS_F64: return mf64_mmax();
     }
     return cls >= 3 ? mf_mmax(cls - 3) : 0;
 }
@@ -546,6 +550,7 @@ int class_threads(int cls) {
         case 0: return C0::NT;
         case 1: return C1::NT;
         case 2: return C2::NT;
+        case RG_CLASS_F64: return mf64_threads();
     }
     return cls >= 3 ? mf_threads(cls - 3) : 0;
 }
@@ -563,7 +568,7 @@ void set_class_rules(const int *m_hi, const int *r_max_hi, const int *cls, int n
 }
 
 int choose_class(int m, int r_max, int dtype) {
-    if (dtype != 0) return -1;  // FP32 state only
+    if (dtype != 0) return mf64_fits(m, r_max) ? RG_CLASS_F64 : -1;  // FP64 state: one class
     for (const ClassRule &rule : g_rules) {
         if (m > rule.m_hi || r_max > rule.r_max_hi) continue;
         if (rule.cls < 0) return -1;
@@ -584,6 +589,7 @@ hipError_t prepare_class(int cls, int rows_alloc) {
         case 0: return prepare<C0>(rows_alloc);
         case 1: return prepare<C1>(rows_alloc);
         case 2: return prepare<C2>(rows_alloc);
+        case RG_CLASS_F64: return mf64_prepare(rows_alloc);
     }
     return cls >= 3 ? mf_prepare(cls - 3, rows_alloc) : hipErrorInvalidValue;
 }
@@ -595,12 +601,12 @@ hipError_t launch_push_class<float>(int cls, const PushArgs<float> &a, int rows_
         case 1: return launch<C1>(a, rows_alloc, s);
         case 2: return launch<C2>(a, rows_alloc, s);
     }
-    return cls >= 3 ? mf_launch(cls - 3, a, rows_alloc, s) : hipErrorInvalidValue;
+    return cls >= 3 && cls < RG_NUM_CLASSES ? mf_launch(cls - 3, a, rows_alloc, s) : hipErrorInvalidValue;
 }
 
 template <>
-hipError_t launch_push_class<double>(int, const PushArgs<double> &, int, hipStream_t) {
-    return hipErrorInvalidValue;
+hipError_t launch_push_class<double>(int cls, const PushArgs<double> &a, int rows_alloc, hipStream_t s) {
+    return cls == RG_CLASS_F64 ? mf64_launch(a, rows_alloc, s) : hipErrorInvalidValue;
 }
 
 }  // namespace rg

@@ -19,6 +19,20 @@ def test_class_table_is_consistent():
         assert not rg.class_fits(c, mcap, rcap + 1)
 
 
+def test_f64_class_shape():
+    """The FP64 on-chip class follows the FP32 classes: rank capacity 64,
+    m up to 128, 256 threads; it takes no placement rules."""
+    from paper_2106_11594_amd import rg
+    c = rg.class_count()
+    assert rg.class_info(c) == (64, 128, 256)
+    assert rg.class_fits(c, 128, 64) and rg.class_fits(c, 1, 1)
+    assert not rg.class_fits(c, 129, 1) and not rg.class_fits(c, 64, 65)
+    with pytest.raises(RuntimeError):
+        rg.class_info(c + 1)
+    with pytest.raises(RuntimeError):
+        rg.set_class_rules([(64, 12, c)])
+
+
 def test_class_rule_validation():
     from paper_2106_11594_amd import rg
     with pytest.raises(RuntimeError):
