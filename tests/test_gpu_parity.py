@@ -75,7 +75,7 @@ def test_single_f64_vs_oracle(n):
     assert h.rank() == ro == 16 and h.flags() == 0
     C, Ct, P, w = _state(h)
     assert np.array_equal(C, Co)
-    assert _rel(x, xo) <= 1e-11
+    assert _rel(x, xo) <= 1e-12  # the plain FP64 stream's bar
     assert _rel(Ct, Cto) <= 1e-10 and _rel(P, Po) <= 1e-10
 
 
