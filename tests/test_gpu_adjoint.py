@@ -59,6 +59,9 @@ def test_adjoint_vs_reference(dtype, tol):
         rA, rY = G.grad_closed_form(Ab, Yb, xr - xtb, r)
         assert _rel(dA[b], rA) <= tol, (b, _rel(dA[b], rA))
         assert _rel(dY[b], rY) <= tol, (b, _rel(dY[b], rY))
+        # element by element, against the largest entry of the reference
+        assert np.abs(dA[b] - rA).max() <= tol * np.abs(rA).max(), b
+        assert np.abs(dY[b] - rY).max() <= tol * np.abs(rY).max(), b
 
 
 def test_adjoint_vs_finite_differences():
@@ -79,6 +82,37 @@ def test_adjoint_vs_finite_differences():
         fd = G.grad_fd(Ab, Yb, loss, r, directions=dirs)
         an = np.array([np.sum(dA[b] * d) + np.sum(dY[b] * e) for d, e in dirs])
         assert np.abs(fd - an).max() <= 1e-4 * max(1.0, np.abs(an).max())
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_adjoint_vs_finite_differences_m64(dtype):
+    """Directional derivatives of a larger problem (m = 64, r = 12, n = 150)
+    against FP64 central differences through the rank-r solve of the values
+    the device received (FP32-rounded for the FP32 run): 1e-4 relative."""
+    import torch
+    from paper_2106_11594_amd.rg import rg_solve
+    B, m, r, n = 2, 64, 12, 150
+    probs = _problems(B, m, r, n, 3)
+    td = torch.float64 if dtype == "f64" else torch.float32
+    A = torch.tensor(np.stack([p[0] for p in probs]), dtype=td, device="cuda", requires_grad=True)
+    Y = torch.tensor(np.stack([p[1] for p in probs]), dtype=td, device="cuda", requires_grad=True)
+    xt = torch.tensor(np.stack([p[2] for p in probs]), dtype=td, device="cuda")
+    x = rg_solve(A, Y, eps=1e-8 if dtype == "f64" else 1e-3)
+    (0.5 * ((x - xt) ** 2).sum()).backward()
+    dA, dY = A.grad.double().cpu().numpy(), Y.grad.double().cpu().numpy()
+    rng = np.random.default_rng(11)
+    for b, (Ab, Yb, xtb) in enumerate(probs):
+        if dtype == "f32":
+            Ab = Ab.astype(np.float32).astype(np.float64)
+            Yb = Yb.astype(np.float32).astype(np.float64)
+            xtb = xtb.astype(np.float32).astype(np.float64)
+        loss = lambda xx: 0.5 * float(np.sum((xx - xtb) ** 2))
+        dirs = [(rng.standard_normal(Ab.shape), rng.standard_normal(Yb.shape)) for _ in range(4)]
+        fd = G.grad_fd(Ab, Yb, loss, r, directions=dirs)
+        an = np.array([np.sum(dA[b] * d) + np.sum(dY[b] * e) for d, e in dirs])
+        err = np.abs(fd - an).max() / max(1.0, np.abs(fd).max())
+        print("%s problem %d: directional derivatives within %.2e of FD" % (dtype, b, err), flush=True)
+        assert err <= 1e-4
 
 
 def test_grad_batch_workload_sampled():
