@@ -93,3 +93,30 @@ def test_f64_batches_stay_in_the_generic_kernel():
     h = rg.Batch(np.array([64, 40], np.int32), dtype="f32", eps=1e-3)
     assert (h.classes() >= 0).all() and (h.classes() < rg.class_count()).all()
     h.close()
+
+
+@pytest.mark.parametrize("opt", ["OPT_ROW_BY_ROW", "OPT_DEPENDENT_BLOCKS_ONLY", "OPT_EXPLICIT_REJECTIONS"])
+def test_f64_class_reference_paths(opt):
+    """The FP64 class's row mode (every row alone) and its dependent-blocks-only
+    and explicit-rejection paths against the oracle; row by row, pushes in
+    pieces repeat the one-push bits."""
+    from paper_2106_11594_amd import rg
+    flag = getattr(rg, opt)
+    rng = np.random.default_rng(91)
+    m, r, n = 72, 20, 330
+    A = W.lowrank_rows(rng, m, r, n)
+    A[40] = A[39]
+    A[200] = A[3] + A[7]
+    Y, _ = W.targets(rng, A)
+    h = rg.Batch(np.array([m], np.int32), r_max=np.array([48], np.int32), dtype="f64", eps=1e-10, flags=flag)
+    assert int(h.classes()[0]) == rg.class_count()
+    h.close()
+    x1, r1, f1 = _solve(A, Y, 48, 1e-10, flags=flag)
+    x2, r2, f2 = _solve(A, Y, 48, 1e-10, flags=flag, chunks=(1, 2, 90, 91, 250))
+    xo, ro, Co, *_ = ref_c.solve(A, Y, eps=1e-10, cap=48)
+    assert f1 == f2 == 0 and r1 == r2 == ro == r
+    tol = max(1e-11, float(np.linalg.cond(Co)) ** 2 * 2.0 ** -52)
+    assert np.linalg.norm(x1 - xo) <= tol * np.linalg.norm(xo)
+    assert np.linalg.norm(x2 - xo) <= tol * np.linalg.norm(xo)
+    if opt == "OPT_ROW_BY_ROW":
+        assert np.array_equal(x1, x2)
