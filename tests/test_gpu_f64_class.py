@@ -120,3 +120,38 @@ def test_f64_class_reference_paths(opt):
     assert np.linalg.norm(x2 - xo) <= tol * np.linalg.norm(xo)
     if opt == "OPT_ROW_BY_ROW":
         assert np.array_equal(x1, x2)
+
+
+def test_f64_class_adjoint_and_pinv():
+    """A one-problem FP64 solve runs in the FP64 class (factored form); its
+    adjoint and its pseudoinverse against the FP64 references."""
+    import torch
+    from oracle import adjoint_ref as G
+    from paper_2106_11594_amd import rg
+    from paper_2106_11594_amd.rg import rg_solve
+    rng = np.random.default_rng(93)
+    m, r, n = 24, 5, 40
+    A = W.lowrank_rows(rng, m, r, n)
+    Y, _ = W.targets(rng, A)
+    xt = rng.standard_normal(m)
+    At = torch.tensor(A[None], dtype=torch.float64, device="cuda", requires_grad=True)
+    Yt = torch.tensor(Y[None], dtype=torch.float64, device="cuda", requires_grad=True)
+    x = rg_solve(At, Yt, eps=1e-8)
+    (0.5 * ((x - torch.tensor(xt[None], device="cuda")) ** 2).sum()).backward()
+    xr = G.solve_rank(A, Y, r)
+    rA, rY = G.grad_closed_form(A, Y, xr - xt, r)
+    dA, dY = At.grad[0].cpu().numpy(), Yt.grad[0].cpu().numpy()
+    assert np.linalg.norm(dA - rA) <= 1e-9 * np.linalg.norm(rA)
+    assert np.linalg.norm(dY - rY) <= 1e-9 * np.linalg.norm(rY)
+    h = rg.Batch(np.array([m], np.int32), dtype="f64", eps=1e-8)
+    assert int(h.classes()[0]) == rg.class_count()
+    Ad = torch.from_numpy(np.ascontiguousarray(A)).cuda()
+    Yd = torch.from_numpy(np.ascontiguousarray(Y)).cuda()
+    rp = torch.tensor([0, n], dtype=torch.int64).cuda()
+    ao = torch.tensor([0], dtype=torch.int64).cuda()
+    h.push(Ad.reshape(-1), Yd, rp, ao)
+    Ap = h.pinv(Ad.reshape(-1), rp, ao).double().cpu().numpy().reshape(m, n)
+    assert int(h.rank()[0]) == r
+    h.close()
+    Asvd = np.linalg.pinv(A, rcond=1e-9)
+    assert np.linalg.norm(Ap - Asvd) <= 1e-10 * np.linalg.norm(Asvd)
