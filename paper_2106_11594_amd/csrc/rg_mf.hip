@@ -249,29 +249,32 @@ __device__ __forceinline__ void push_stream(const PushArgs<typename K::E> &a, in
     // Raw tile loads (HG): unconditional, element 0 for entries past rr, so that
     // the loads of several tiles are in flight together; hmask zeroes those
     // entries where the tile is used.
-    auto hraw = [&](int u2, int ups, int rr) -> d4 {
-        const int col = 16 * (wv + NW * ups) + (lane & 15);
+    // (the _t forms name the column tile ut and take the rows rlo .. rlim-1 only, rlim <= rr)
+    auto hraw_t = [&](int u2, int ut, int rr, int rlo, int rlim) -> d4 {
+        const int col = 16 * ut + (lane & 15);
         d4 o;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int row = 16 * u2 + 4 * v + (lane >> 4);
-            const bool in = row < rr && col < rr;
+            const bool in = row >= rlo && row < rlim && col < rr;
             int64_t idx = in ? (int64_t)row * rmax + col : 0;
             asm("" : "+v"(idx));
             o[v] = Hg[idx];
         }
         return o;
     };
-    auto hmask = [&](int u2, int ups, int rr, const d4 &raw) -> d4 {
-        const int col = 16 * (wv + NW * ups) + (lane & 15);
+    auto hmask_t = [&](int u2, int ut, int rr, int rlo, int rlim, const d4 &raw) -> d4 {
+        const int col = 16 * ut + (lane & 15);
         d4 o;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int row = 16 * u2 + 4 * v + (lane >> 4);
-            o[v] = row < rr && col < rr ? raw[v] : 0.0;
+            o[v] = row >= rlo && row < rlim && col < rr ? raw[v] : 0.0;
         }
         return o;
     };
+    auto hraw = [&](int u2, int ups, int rr) -> d4 { return hraw_t(u2, wv + NW * ups, rr, 0, rr); };
+    auto hmask = [&](int u2, int ups, int rr, const d4 &raw) -> d4 { return hmask_t(u2, wv + NW * ups, rr, 0, rr, raw); };
     auto hload = [&](int u2, int ups, int rr) -> d4 {
         if constexpr (K::HG) {
             return hmask(u2, ups, rr, hraw(u2, ups, rr));
@@ -377,9 +380,59 @@ __device__ __forceinline__ void push_stream(const PushArgs<typename K::E> &a, in
 
             // ---- V = Gamma_blk C^T: tiles u = wv + NW ups of V^T ----
             const int nur = (r + 15) / 16;
+            // SIMD balance of the RMAX = 128 variants (one tile per wave, wave w on
+            // SIMD w % 4).  With nur = 5 or 6 tiles, the waves w >= nur would idle
+            // while SIMDs 0 and 1 carry two tiles each: they take pieces instead.
+            // Tile 4 (nur = 5) is cut into 4 pieces of its inner dimension, tiles 4
+            // and 5 (nur = 6) into 2, piece 0 staying with the tile's own wave and
+            // piece p >= 1 going to wave nur + (p - 1) kx + (tile - 4); the pieces
+            // meet in LDS in the free tile slots past nur and are summed in piece
+            // order by the tile's own wave (a fixed order).  Every SIMD then carries
+            // 1.25 or 1.5 tiles of V and of G = V H^-1.
+            const int kx = nur - 4;
+            const bool split = K::HG && (kx == 1 || kx == 2);
+            int vt = wv, vp = 0, vpt = 1;  // this wave's tile, its piece, the tile's pieces
+            if (split) {
+                if (wv >= nur) {
+                    vt = 4 + (wv - nur) % kx;
+                    vp = 1 + (wv - nur) / kx;
+                }
+                if (vt >= 4) vpt = 4 / kx;
+            }
+            const int vslot = vp == 0 ? vt : nur + (vp - 1) * kx + (vt - 4);  // LDS tile slot of the result
             d4 gacc[UPW];
             double gsq = 0.0;
-            {
+            if constexpr (K::HG) {
+                d4 ga0 = (d4){0.0, 0.0, 0.0, 0.0}, ga1 = ga0;
+                const int qs = vp * nq / vpt, qe = (vp + 1) * nq / vpt;
+                const E *gbase = x1f + li * MMAX;
+                if (vt < nur && qs < qe) {
+                    const E *cb = sct + (size_t)(16 * vt + li) * MMAX;
+                    const int ph0 = (4 * qs + lg) ^ li;
+                    V4 gb = *reinterpret_cast<const V4 *>(gbase + 4 * ph0);
+                    V4 ca = *reinterpret_cast<const V4 *>(cb + 4 * ph0);
+#pragma unroll 1
+                    for (int q = qs; q < qe; ++q) {
+                        const V4 gq = gb, cq = ca;
+                        if (q + 1 < qe) {
+                            const int phn = (4 * q + 4 + lg) ^ li;
+                            gb = *reinterpret_cast<const V4 *>(gbase + 4 * phn);
+                            ca = *reinterpret_cast<const V4 *>(cb + 4 * phn);
+                        }
+                        ga0 = mma((double)cq.x, (double)gq.x, ga0);
+                        ga1 = mma((double)cq.y, (double)gq.y, ga1);
+                        ga0 = mma((double)cq.z, (double)gq.z, ga0);
+                        ga1 = mma((double)cq.w, (double)gq.w, ga1);
+                    }
+                }
+                gacc[0] = ga0 + ga1;
+#pragma unroll 1
+                for (int q = wv; q < nq; q += NW) {  // this wave's share of ||Gamma_i||^2
+                    const V4 gq = *reinterpret_cast<const V4 *>(gbase + 4 * ((4 * q + lg) ^ li));
+                    const double b0 = gq.x, b1 = gq.y, b2 = gq.z, b3 = gq.w;
+                    gsq += b0 * b0 + b1 * b1 + b2 * b2 + b3 * b3;
+                }
+            } else {
                 d4 gacc2[UPW];
 #pragma unroll
                 for (int ups = 0; ups < UPW; ++ups) gacc[ups] = gacc2[ups] = (d4){0.0, 0.0, 0.0, 0.0};
@@ -427,6 +480,12 @@ __device__ __forceinline__ void push_stream(const PushArgs<typename K::E> &a, in
             // this wave's share of ||Gamma_i||^2 (chunks wv, wv + NW, ...); the
             // shares are summed after the projections, in a fixed order
             gsq = sum_rows(gsq);
+            if constexpr (K::HG) {
+                if (vt < nur) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) x2[gpos<RMAX>(li, 16 * vslot + 4 * v + lg)] = gacc[0][v];
+                }
+            } else {
 #pragma unroll
             for (int ups = 0; ups < UPW; ++ups) {
                 const int u = wv + NW * ups;
@@ -435,6 +494,7 @@ __device__ __forceinline__ void push_stream(const PushArgs<typename K::E> &a, in
                     for (int v = 0; v < 4; ++v) x2[gpos<RMAX>(li, 16 * u + 4 * v + lg)] = gacc[ups][v];
                 }
             }
+            }
             double gi[TPW][4];  // Gamma_blk[i][16 tl + 4 v + g] for this wave's column tiles
 #pragma unroll
             for (int tau = 0; tau < TPW; ++tau)
@@ -442,25 +502,44 @@ __device__ __forceinline__ void push_stream(const PushArgs<typename K::E> &a, in
                 for (int v = 0; v < 4; ++v)
                     gi[tau][v] = wv + NW * tau < NTT ? (double)x1f[li * MMAX + 4 * ((4 * (wv + NW * tau) + v) ^ li) + lg] : 0.0;
             __syncthreads();
+            if (split) {
+                // V tiles 4 .. nur-1: the tile's own wave adds the other pieces
+                if (wv >= 4 && wv < nur) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        double sv = x2[gpos<RMAX>(li, 16 * wv + 4 * v + lg)];
+#pragma unroll
+                        for (int pp = 1; pp < 4; ++pp)
+                            if (pp < vpt) sv += x2[gpos<RMAX>(li, 16 * (nur + (pp - 1) * kx + (wv - 4)) + 4 * v + lg)];
+                        x2[gpos<RMAX>(li, 16 * wv + 4 * v + lg)] = sv;
+                    }
+                }
+                __syncthreads();
+            }
 
             // ---- G^T = H^-1 V^T on this wave's row tiles (H^-1 symmetric) ----
 #pragma unroll
             for (int ups = 0; ups < UPW; ++ups) {
                 const int u = wv + NW * ups;
                 gacc[ups] = (d4){0.0, 0.0, 0.0, 0.0};
-                if (u < nur) {
+                if ((K::HG ? vt : u) < nur) {
                     d4 g2acc = (d4){0.0, 0.0, 0.0, 0.0};
                     if constexpr (K::HG) {
-                        // tiles of H^-1 from L2, HB tiles' loads in flight at a time
+                        // tiles of H^-1 from L2, HB tiles' loads in flight at a time;
+                        // this wave's piece takes the V tiles gs .. ge-1 of tile vt (the
+                        // batches stay aligned to HB; tiles outside the piece read as zero)
                         constexpr int HB = 4;
+                        const int gs = vp * nur / vpt, ge = (vp + 1) * nur / vpt;
+                        const int rlo = 16 * gs, rlim = min(r, 16 * ge);
 #pragma unroll 1
-                        for (int ub = 0; ub < nur; ub += HB) {
+                        for (int ub = 0; ub < ge; ub += HB) {
                             d4 ht[HB];
 #pragma unroll
-                            for (int q = 0; q < HB; ++q) ht[q] = hload(ub + q, ups, r);
+                            for (int q = 0; q < HB; ++q)
+                                ht[q] = hmask_t(ub + q, vt, r, rlo, rlim, hraw_t(ub + q, vt, r, rlo, rlim));
 #pragma unroll
                             for (int q = 0; q < HB; ++q)
-                                if (ub + q < nur)
+                                if (ub + q >= gs && ub + q < ge)
 #pragma unroll
                                     for (int v = 0; v < 4; v += 2) {
                                         gacc[ups] = mma(ht[q][v], x2[gpos<RMAX>(li, 16 * (ub + q) + 4 * v + lg)], gacc[ups]);
@@ -481,6 +560,22 @@ __device__ __forceinline__ void push_stream(const PushArgs<typename K::E> &a, in
                         }
                     }
                     gacc[ups] += g2acc;
+                }
+            }
+            if (split) {
+                // G tiles 4 .. nur-1: the pieces go to the free slots past nur (V
+                // stays in the slots below nur), the tile's own wave adds them
+                if (vp > 0) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) x2[gpos<RMAX>(li, 16 * vslot + 4 * v + lg)] = gacc[0][v];
+                }
+                __syncthreads();
+                if (wv >= 4 && wv < nur) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+#pragma unroll
+                        for (int pp = 1; pp < 4; ++pp)
+                            if (pp < vpt) gacc[0][v] += x2[gpos<RMAX>(li, 16 * (nur + (pp - 1) * kx + (wv - 4)) + 4 * v + lg)];
                 }
             }
             // this wave's parts of gamma_i^T v_i, ||gamma_i||^2 and ||v_i||^2 (V is still in X2)
