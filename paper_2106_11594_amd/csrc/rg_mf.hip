@@ -958,6 +958,7 @@ __device__ __forceinline__ void push_stream(const PushArgs<typename K::E> &a, in
                     const double inv = rsqrt_f64(piv), lkk = piv * inv;
                     const double ck = cyk * inv;
                     const double lik = srow[k] * inv;  // L[i][k] for i > k
+                    const double fik = lik * inv;      // S[i][k] / S[k][k]: one product per trailing entry
                     if (li == k) {
                         mypiv = piv;
                         myc = ck;
@@ -966,7 +967,7 @@ __device__ __forceinline__ void push_stream(const PushArgs<typename K::E> &a, in
                     srow[k] = li == k ? lkk : (li > k ? lik : 0.0);
                     if (li > k) cy -= lik * ck;
 #pragma unroll
-                    for (int j = k + 1; j < 16; ++j) srow[j] -= lik * (cv[j] * inv);
+                    for (int j = k + 1; j < 16; ++j) srow[j] -= fik * cv[j];
                 }
                 if (!indblk) {
                 const uint64_t badp = __ballot(!(mypiv > 0.0 && isfinite(mypiv))) & 0xFFFFull;
