@@ -964,8 +964,11 @@ __device__ __forceinline__ void push_stream(const PushArgs<typename K::E> &a, in
                         myc = ck;
                         myinv = inv;
                     }
-                    srow[k] = li == k ? lkk : (li > k ? lik : 0.0);
-                    if (li > k) cy -= lik * ck;
+                    // Entries of the rows above k (lanes i < k) and their c are never
+                    // read again: they are updated like the others instead of being
+                    // masked, and only the lower triangle of L is used.
+                    srow[k] = li == k ? lkk : lik;
+                    cy -= lik * ck;
 #pragma unroll
                     for (int j = k + 1; j < 16; ++j) srow[j] -= fik * cv[j];
                 }
