@@ -1166,18 +1166,33 @@ __device__ __forceinline__ void push_stream(const PushArgs<typename K::E> &a, in
 #pragma unroll
                 for (int j = 0; j < 16; ++j) tr[j] = x2[zpos(tl, j)];
                 double dw = 0.0;
+                // the entries of row j + 1 of L (with its 1/L[j+1][j+1] and c) are
+                // requested before row j is used, so that each step's LDS reads are
+                // in flight during the step before it
+                double2 ln[8];
+                double invn = x1[K::X1_C + 16], cn = x1[K::X1_C];
 #pragma unroll
                 for (int j = 0; j < 16; ++j) {
+                    double2 lc[8];
+#pragma unroll
+                    for (int e = 0; e < (j + 1) / 2; ++e) lc[e] = ln[e];
+                    const double invj = invn, cj = cn;
+                    if (j + 1 < 16) {
+                        const double2 *lrow = reinterpret_cast<const double2 *>(x1 + K::X1_L + 16 * (j + 1));
+#pragma unroll
+                        for (int e = 0; e < (j + 2) / 2; ++e) ln[e] = lrow[e];
+                        invn = x1[K::X1_C + 16 + j + 1];
+                        cn = x1[K::X1_C + j + 1];
+                    }
                     double a0 = tr[j], a1 = 0.0;
-                    const double2 *lrow = reinterpret_cast<const double2 *>(x1 + K::X1_L + 16 * j);
 #pragma unroll
                     for (int j2 = 0; j2 < j; j2 += 2) {
-                        const double2 l2 = lrow[j2 / 2];
+                        const double2 l2 = lc[j2 / 2];
                         a0 -= tr[j2] * l2.x;
                         if (j2 + 1 < j) a1 -= tr[j2 + 1] * l2.y;
                     }
-                    tr[j] = j < ndd ? (a0 + a1) * x1[K::X1_C + 16 + j] : 0.0;
-                    dw += tr[j] * x1[K::X1_C + j];
+                    tr[j] = j < ndd ? (a0 + a1) * invj : 0.0;
+                    dw += tr[j] * cj;
                 }
 #pragma unroll
                 for (int j = 0; j < 16; ++j) x2[zpos(tl, j)] = tr[j];
