@@ -402,27 +402,39 @@ __device__ __forceinline__ void push_stream(const PushArgs<typename K::E> &a, in
             const int vslot = vp == 0 ? vt : nur + (vp - 1) * kx + (vt - 4);  // LDS tile slot of the result
             d4 gacc[UPW];
             double gsq = 0.0;
-            if constexpr (K::HG) {
+            if constexpr (UPW == 1) {
+                // chunk 4q + g of a row with (row & 15) == i sits at physical chunk (4q + g) ^ i
                 d4 ga0 = (d4){0.0, 0.0, 0.0, 0.0}, ga1 = ga0;
                 const int qs = vp * nq / vpt, qe = (vp + 1) * nq / vpt;
                 const E *gbase = x1f + li * MMAX;
                 if (vt < nur && qs < qe) {
                     const E *cb = sct + (size_t)(16 * vt + li) * MMAX;
-                    const int ph0 = (4 * qs + lg) ^ li;
-                    V4 gb = *reinterpret_cast<const V4 *>(gbase + 4 * ph0);
-                    V4 ca = *reinterpret_cast<const V4 *>(cb + 4 * ph0);
-#pragma unroll 1
-                    for (int q = qs; q < qe; ++q) {
-                        const V4 gq = gb, cq = ca;
-                        if (q + 1 < qe) {
-                            const int phn = (4 * q + 4 + lg) ^ li;
-                            gb = *reinterpret_cast<const V4 *>(gbase + 4 * phn);
-                            ca = *reinterpret_cast<const V4 *>(cb + 4 * phn);
-                        }
+                    auto ldg = [&](int q) { return *reinterpret_cast<const V4 *>(gbase + 4 * ((4 * q + lg) ^ li)); };
+                    auto ldc = [&](int q) { return *reinterpret_cast<const V4 *>(cb + 4 * ((4 * q + lg) ^ li)); };
+                    // two accumulators, so that consecutive products do not wait on each other
+                    auto prod = [&](const V4 &gq, const V4 &cq) {
                         ga0 = mma((double)cq.x, (double)gq.x, ga0);
                         ga1 = mma((double)cq.y, (double)gq.y, ga1);
                         ga0 = mma((double)cq.z, (double)gq.z, ga0);
                         ga1 = mma((double)cq.w, (double)gq.w, ga1);
+                    };
+                    // two operand buffers: the loads of chunk q + 1 are in flight while
+                    // chunk q is multiplied (past the range they load chunk qe - 1 again);
+                    // the scheduling barriers keep the compiler from moving the loads
+                    // down to their first use
+                    V4 g0 = ldg(qs), c0 = ldc(qs);
+#pragma unroll 1
+                    for (int q = qs; q < qe; q += 2) {
+                        const int q1 = min(q + 1, qe - 1);
+                        const V4 g1 = ldg(q1), c1 = ldc(q1);
+                        __builtin_amdgcn_sched_barrier(0);
+                        prod(g0, c0);
+                        if (q + 1 >= qe) break;
+                        const int q2 = min(q + 2, qe - 1);
+                        g0 = ldg(q2);
+                        c0 = ldc(q2);
+                        __builtin_amdgcn_sched_barrier(0);
+                        prod(g1, c1);
                     }
                 }
                 gacc[0] = ga0 + ga1;
@@ -480,7 +492,7 @@ __device__ __forceinline__ void push_stream(const PushArgs<typename K::E> &a, in
             // this wave's share of ||Gamma_i||^2 (chunks wv, wv + NW, ...); the
             // shares are summed after the projections, in a fixed order
             gsq = sum_rows(gsq);
-            if constexpr (K::HG) {
+            if constexpr (UPW == 1) {
                 if (vt < nur) {
 #pragma unroll
                     for (int v = 0; v < 4; ++v) x2[gpos<RMAX>(li, 16 * vslot + 4 * v + lg)] = gacc[0][v];
