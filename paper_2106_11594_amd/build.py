@@ -13,11 +13,17 @@ SOURCES = ["rg_api.hip", "rg_generic.hip", "rg_rk.hip", "rg_mf.hip", "rg_big.hip
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Per-file additions.  The blocked kernel's variants with one wave per SIMD
+# have 512 registers per lane; by default the compiler then gives the
+# matrix-core products accumulators in the AGPR half and copies every
+# loop-carried accumulator back and forth each iteration.  The VGPR form of
+# the products keeps them in place (the AGPRs then only hold spills).
+EXTRA = {"rg_mf.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def _compile(src):
     obj = os.path.join(OBJ, src + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     p = subprocess.run(cmd, capture_output=True, text=True)
     err = "\n".join(l for l in p.stderr.splitlines() if "packed-fp32-ops" not in l)
     if p.returncode != 0:

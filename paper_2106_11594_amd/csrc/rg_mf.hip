@@ -421,21 +421,22 @@ __device__ __forceinline__ void push_stream(const PushArgs<typename K::E> &a, in
                     // two operand buffers: the loads of chunk q + 1 are in flight while
                     // chunk q is multiplied (past the range they load chunk qe - 1 again);
                     // the scheduling barriers keep the compiler from moving the loads
-                    // down to their first use
+                    // down to their first use, and the loop has a single exit so that
+                    // the accumulators stay where the products write them
                     V4 g0 = ldg(qs), c0 = ldc(qs);
+                    int q = qs;
 #pragma unroll 1
-                    for (int q = qs; q < qe; q += 2) {
-                        const int q1 = min(q + 1, qe - 1);
-                        const V4 g1 = ldg(q1), c1 = ldc(q1);
+                    for (; q + 1 < qe; q += 2) {
+                        const V4 g1 = ldg(q + 1), c1 = ldc(q + 1);
                         __builtin_amdgcn_sched_barrier(0);
                         prod(g0, c0);
-                        if (q + 1 >= qe) break;
                         const int q2 = min(q + 2, qe - 1);
                         g0 = ldg(q2);
                         c0 = ldc(q2);
                         __builtin_amdgcn_sched_barrier(0);
                         prod(g1, c1);
                     }
+                    if (q < qe) prod(g0, c0);  // an odd last chunk (already loaded)
                 }
                 gacc[0] = ga0 + ga1;
 #pragma unroll 1
