@@ -643,12 +643,21 @@ __device__ __forceinline__ void push_stream(const PushArgs<typename K::E> &a, in
             {
                 double cgv = 0.0, cgg = 0.0, cvv = 0.0;
                 gsq = 0.0;  // ||Gamma_i||^2
+                // all records are requested before they are summed (the scheduling
+                // barrier keeps the compiler from moving each read down to its sum,
+                // which would serialise the reads)
+                double rec[4][NW];
+#pragma unroll
+                for (int q = 0; q < NW; ++q)
+#pragma unroll
+                    for (int f = 0; f < 4; ++f) rec[f][q] = x1[K::X1_CT + 16 * NW * f + 16 * q + li];
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int q = 0; q < NW; ++q) {
-                    cgv += x1[K::X1_CT + 16 * q + li];
-                    cgg += x1[K::X1_CT + 16 * NW + 16 * q + li];
-                    cvv += x1[K::X1_CT + 32 * NW + 16 * q + li];
-                    gsq += x1[K::X1_CT + 48 * NW + 16 * q + li];
+                    cgv += rec[0][q];
+                    cgg += rec[1][q];
+                    cvv += rec[2][q];
+                    gsq += rec[3][q];
                 }
                 const double eps0 = a.eps >= 0.0 ? a.eps : ((double)m * m * r + (double)m * r + (double)m) * 0x1p-52;
                 const double est = gsq - cgv;
@@ -843,11 +852,20 @@ __device__ __forceinline__ void push_stream(const PushArgs<typename K::E> &a, in
             double g2row;  // ||Gamma_i||^2 of block row i
             double r2row;  // ||R_i||^2: its rejection against the span of C
             bool badrow;   // block row i or its target is not finite
+            // the records of ||R_i||^2 and (G w)_i are requested together before they
+            // are summed (as for the certificate above)
+            double rrec[NW], wrec[NW];
+#pragma unroll
+            for (int q = 0; q < NW; ++q) {
+                rrec[q] = x1[K::X1_RR + 16 * q + li];
+                wrec[q] = x1[K::X1_GW + 16 * q + li];
+            }
+            const double g2 = x1[K::X1_GG + li], yj = x1[K::X1_YV + li];
+            __builtin_amdgcn_sched_barrier(0);
             {
                 double r2 = 0.0;
 #pragma unroll
-                for (int q = 0; q < NW; ++q) r2 += x1[K::X1_RR + 16 * q + li];
-                const double g2 = x1[K::X1_GG + li], yj = x1[K::X1_YV + li];
+                for (int q = 0; q < NW; ++q) r2 += rrec[q];
                 const bool bad = li < nblk && (!isfinite(g2) || !isfinite(yj));
                 g2row = g2;
                 r2row = r2;
@@ -861,7 +879,7 @@ __device__ __forceinline__ void push_stream(const PushArgs<typename K::E> &a, in
             }
             double gwi = 0.0;
 #pragma unroll
-            for (int q = 0; q < NW; ++q) gwi += x1[K::X1_GW + 16 * q + li];
+            for (int q = 0; q < NW; ++q) gwi += wrec[q];
             const double dyi = yrow - gwi;
             if (nd == 0 && (stop || !ind_blocks)) {
                 if (stop) {
