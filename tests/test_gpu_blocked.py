@@ -263,3 +263,37 @@ def test_certified_skip_vs_explicit_rejections(dtype):
         assert eb <= tol, (k, eb)
         worst, between = max(worst, e1, e2), max(between, eb)
     print("%s: worst vs oracle %.2e, between the modes %.2e" % (dtype, worst, between), flush=True)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("m,r", [(240, 72), (240, 88), (180, 88), (240, 104)])
+def test_rank_tiles_split_over_simds(m, r):
+    """Streams whose rank fills 5 (r = 72) or 6 (r = 88) row tiles of 16 in the
+    RMAX = 128 variants: the waves past the last tile take pieces of the inner
+    dimension of V = Gamma C^T and G = V H^-1, which meet in LDS; 7 tiles
+    (r = 104) are not split.  Six streams per case, blocked against row by
+    row and against the FP64 oracle: ranks exact, x within the FP32 bound."""
+    from paper_2106_11594_amd import rg
+    from tests.gpu_util import run_batch
+    rng = np.random.default_rng(1000 * m + r)
+    streams = []
+    for k in range(6):
+        A = _f32(W.lowrank_rows(rng, m, r, 3 * m + 37 + 11 * k))
+        Y, _ = W.targets(rng, A)
+        streams.append((A, _f32(Y)))
+    ms, ns, row_ptr, a_off, Ap, Yp = W.pack(streams, 1e-3, "f32")
+    bt = W.Batch(ms, np.full(6, r, np.int32), ns, row_ptr, a_off, Ap, Yp, 1e-3, "f32", {})
+    r_max = np.full(6, r + 4, np.int32)
+    xb, rb, fb, hb = run_batch(bt, "f32", r_max=r_max, eps=1e-3)
+    cls = hb.classes()
+    hb.close()
+    assert all(rg.class_info(int(c))[0] == 128 for c in cls), cls  # an RMAX = 128 variant
+    xr, rr, fr, hr = run_batch(bt, "f32", r_max=r_max, eps=1e-3, flags=rg.OPT_ROW_BY_ROW)
+    hr.close()
+    assert (fb == 0).all() and (fr == 0).all()
+    for b, (A, Y) in enumerate(streams):
+        xo, ro, Co, *_ = ref_c.solve(A, Y, eps=1e-3, cap=r + 4)
+        tol, kap = _kappa_tol(Co)
+        assert rb[b] == rr[b] == ro == r, b
+        assert _rel(xb[b], xo) <= tol and _rel(xr[b], xo) <= tol, (b, kap, _rel(xb[b], xo))
+        assert _rel(xb[b], xr[b]) <= tol, b
