@@ -147,6 +147,15 @@ struct BigArgs {
 constexpr int BW = 512;
 constexpr int NWB = BW / 64;
 constexpr int UB = 8;
+// V = Gamma_blk C^T of FP64 streams: each 16-column tile of V is split over
+// vsplit workgroups along the columns of C (a stream of a few hundred rows
+// then occupies four times as many CUs); k_bb_g adds the partial tiles in
+// split order.  FP32 streams keep one workgroup per tile (splitting them
+// gained nothing for m = 2048 and lost 2 % for m = 1024).  The scratch holds
+// VS_MAX partial tiles either way.
+constexpr int VS_MAX = 4;
+template <typename T>
+constexpr int vsplit() { return sizeof(T) == 8 ? 4 : 1; }
 static_assert(NWB % 4 == 0, "four column tiles per slice");
 
 // Sum of the waves' 16 x 16 tiles (d4 per lane) into wave 0 (fixed order).
@@ -171,10 +180,14 @@ __device__ void v_tiles(const BigArgs<T> &b, int r0, int nb, const T *gb, int nt
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, li = lane & 15, lg = lane >> 4;
     constexpr int UV = sizeof(T) == 4 ? 8 : 4;  // groups per wave and batch
     const int ngrp = (b.m + 15) / 16;
-    const int nit = (ngrp - wid + NWB - 1) / NWB;
     const bool grow = li < nb;
     const T *grw = gb + (int64_t)(grow ? li : 0) * b.m;
-    for (int t = blockIdx.x; 16 * t < r0; t += ntw) {
+    constexpr int VS = vsplit<T>();
+    const int ntiles = (r0 + 15) / 16;
+    for (int item = blockIdx.x; item < ntiles * VS; item += ntw) {
+        const int t = item / VS, sp = item - t * VS;  // tile, split of the columns
+        const int g0 = sp * ngrp / VS, g1 = (sp + 1) * ngrp / VS;
+        const int nit = (g1 - g0 - wid + NWB - 1) / NWB;
         const int a0 = 16 * t;
         const bool crok = a0 + li < r0;
         const T *crow = b.C + (size_t)(crok ? a0 + li : 0) * b.ldm;
@@ -184,7 +197,7 @@ __device__ void v_tiles(const BigArgs<T> &b, int r0, int nb, const T *gb, int nt
 #pragma unroll
             for (int u = 0; u < UV; ++u) {
                 const bool itok = it0 + u < nit;
-                const int c = 16 * (wid + NWB * (it0 + u)) + 4 * lg;
+                const int c = 16 * (g0 + wid + NWB * (it0 + u)) + 4 * lg;
                 ld4(crow + ((itok && c < b.ldm) ? c : 0), cv[u]);
                 if constexpr (GV) {
                     ld4(grw + ((itok && c < b.m) ? c : 0), gv[u]);
@@ -208,7 +221,7 @@ __device__ void v_tiles(const BigArgs<T> &b, int r0, int nb, const T *gb, int nt
         // D[4v + lg][li] = V[j = 4v + lg][a0 + li]
         if (wid == 0 && crok)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) b.V[(size_t)(4 * v + lg) * b.rmax + a0 + li] = acc[v];
+            for (int v = 0; v < 4; ++v) b.V[((size_t)sp * KB + 4 * v + lg) * b.rmax + a0 + li] = acc[v];
         __syncthreads();
     }
 }
@@ -294,7 +307,10 @@ __global__ void __launch_bounds__(BW) k_bb_g(BigArgs<T> b, int64_t blk) {
             for (int u = 0; u < UB; ++u) {
                 const int a = 4 * (wid + NWB * (it0 + u)) + lg;
                 const bool ok = it0 + u < nit && a < r0;
-                av[u] = ld_or0(b.V, (int64_t)li * b.rmax + a, ok);
+                double sv = 0.0;
+#pragma unroll
+                for (int sp = 0; sp < vsplit<T>(); ++sp) sv += ld_or0(b.V, ((int64_t)sp * KB + li) * b.rmax + a, ok);
+                av[u] = sv;
                 bv[u] = ld_or0(b.H, (int64_t)a * b.rmax + b0 + li, ok && colok);
             }
 #pragma unroll
@@ -1101,7 +1117,7 @@ BigLayout big_layout(int m, int rmax) {
     L.sm = off;
     off += SM_SIZE;
     L.V = off;
-    off += (size_t)KB * rmax;
+    off += (size_t)VS_MAX * KB * rmax;
     L.G = off;
     off += (size_t)KB * rmax;
     L.Z = off;
@@ -1156,7 +1172,7 @@ hipError_t launch_push_big(const PushArgs<T> &a, const StreamMeta &M, double *sc
     b.Q = scratch + L.Q;
     b.sm = scratch + L.sm;
     const int tiles16 = (M.r_max + 15) / 16;
-    const int g_v = std::min(tiles16, 2 * num_cus) + KB;
+    const int g_v = std::min(tiles16 * vsplit<T>(), 2 * num_cus) + KB;
     const int g_g = std::min(tiles16, 2 * num_cus);
     const int ns_grid = std::min(b.ns, 2 * num_cus);
     const int g_rz = ns_grid + std::min(tiles16, 2 * num_cus);
