@@ -44,11 +44,12 @@ def kernel_digest():
     counter-based traffic figure is valid only for the build it was taken on."""
     import hashlib
     d = os.path.join(ROOT, "paper_2106_11594_amd")
-    # rg_pinv_track.hip holds no kernel of the push, so it does not enter the digest.
+    # rg_pinv_track.hip and rg_big.hip (the one-stream path) hold no kernel of the
+    # batched push, so they do not enter the digest; the build flags do.
     files = sorted(f for f in os.listdir(os.path.join(d, "csrc"))
-                   if f.endswith((".hip", ".h")) and f != "rg_pinv_track.hip")
+                   if f.endswith((".hip", ".h")) and f not in ("rg_pinv_track.hip", "rg_big.hip"))
     hsh = hashlib.sha256()
-    for f in [os.path.join("csrc", f) for f in files] + ["class_rules.json"]:
+    for f in [os.path.join("csrc", f) for f in files] + ["class_rules.json", "build.py"]:
         path = os.path.join(d, f)
         if os.path.exists(path):
             hsh.update(f.encode())
