@@ -237,7 +237,7 @@ __global__ void __launch_bounds__(BW) k_bb_v(BigArgs<T> b, int64_t blk) {
     const int r0 = ctl->rank[s];
     const int64_t i0 = blk * b.kb;
     const int nb = (int)min((int64_t)b.kb, b.n - i0);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, li = lane & 15, lg = lane >> 4;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const T *gb = b.gam + i0 * b.m;
     const int ntw = gridDim.x - KB;  // the last KB workgroups take one block row each
     if ((int)blockIdx.x >= ntw) {
