@@ -340,6 +340,29 @@ __device__ inline void hmul(const double *H, int rmax, const double *v, double *
     }
 }
 
+// The same for k_solution, whose sums take SU terms per step with their
+// loads all in flight together (clamped indices past r, masked) and add
+// them in l order: each step of the plain loop waited for its load.
+constexpr int SU = 8;
+__device__ inline void hmul_batched(const double *H, int rmax, const double *v, double *dst, int r) {
+    for (int k = threadIdx.x; k < r; k += NT) {
+        double acc = 0.0;
+        for (int l0 = 0; l0 < r; l0 += SU) {
+            double hv[SU], vv[SU];
+#pragma unroll
+            for (int e = 0; e < SU; ++e) {
+                const int l = l0 + e < r ? l0 + e : r - 1;
+                hv[e] = H[(size_t)l * rmax + k];
+                vv[e] = v[l];
+            }
+#pragma unroll
+            for (int e = 0; e < SU; ++e)
+                if (l0 + e < r) acc += hv[e] * vv[e];
+        }
+        dst[k] = acc;
+    }
+}
+
 // x_b = Ct_b^T w_b, FP64 sums, one workgroup per stream.  Factored-form
 // streams (Ct = H^-1 C) first form u = H^-1 w, then x = C^T u.
 template <typename T>
@@ -350,7 +373,7 @@ __global__ void __launch_bounds__(NT) k_solution(const StreamMeta *meta, const T
     const double *w = wreg + M.w_off;
     const T *B;
     if (M.h_off >= 0) {
-        hmul(hreg + M.h_off, M.r_max, w, su, M.r);
+        hmul_batched(hreg + M.h_off, M.r_max, w, su, M.r);
         __syncthreads();
         w = su;
         B = state + M.state_off;
@@ -359,7 +382,18 @@ __global__ void __launch_bounds__(NT) k_solution(const StreamMeta *meta, const T
     }
     for (int j = threadIdx.x; j < M.m; j += NT) {
         double acc = 0.0;
-        for (int k = 0; k < M.r; ++k) acc += (double)B[(size_t)k * M.ldm + j] * w[k];
+        for (int k0 = 0; k0 < M.r; k0 += SU) {
+            double bv[SU], wv[SU];
+#pragma unroll
+            for (int e = 0; e < SU; ++e) {
+                const int k = k0 + e < M.r ? k0 + e : M.r - 1;
+                bv[e] = (double)B[(size_t)k * M.ldm + j];
+                wv[e] = w[k];
+            }
+#pragma unroll
+            for (int e = 0; e < SU; ++e)
+                if (k0 + e < M.r) acc += bv[e] * wv[e];
+        }
         x[M.x_off + j] = (T)acc;
     }
 }
