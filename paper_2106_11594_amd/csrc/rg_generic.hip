@@ -440,13 +440,22 @@ __global__ void __launch_bounds__(NT) k_adjoint(const StreamMeta *meta, const T 
     double *sh = sv2 + r_max_max, *sh2 = sh + r_max_max;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     if (fd) {
-        hmul(H, rmax, w, sh, r);  // x = C^T (H^-1 w)
+        hmul_batched(H, rmax, w, sh, r);  // x = C^T (H^-1 w)
         __syncthreads();
     }
     const double *wx = fd ? sh : w;
+    // (the sums over k below take SU terms per step with their loads in flight
+    // together, in k order, as in k_solution)
     for (int j = tid; j < m; j += NT) {
         double acc = 0.0;
-        for (int k = 0; k < r; ++k) acc += (double)Ct[(size_t)k * ldm + j] * wx[k];
+        for (int k0 = 0; k0 < r; k0 += SU) {
+            double cv[SU];
+#pragma unroll
+            for (int e = 0; e < SU; ++e) cv[e] = (double)Ct[(size_t)(k0 + e < r ? k0 + e : r - 1) * ldm + j];
+#pragma unroll
+            for (int e = 0; e < SU; ++e)
+                if (k0 + e < r) acc += cv[e] * wx[k0 + e];
+        }
         sx[j] = acc;
         sg[j] = (double)g[M.x_off + j];
     }
@@ -455,35 +464,51 @@ __global__ void __launch_bounds__(NT) k_adjoint(const StreamMeta *meta, const T 
     project<T, double>(Ct, ldm, sx, fd ? sh2 : sv, r, m);
     __syncthreads();
     if (fd) {
-        hmul(H, rmax, sh, su, r);
-        hmul(H, rmax, sh2, sv, r);
+        hmul_batched(H, rmax, sh, su, r);
+        hmul_batched(H, rmax, sh2, sv, r);
         __syncthreads();
     }
     for (int i = tid; i < r; i += NT) {
         double a1 = 0.0, a2 = 0.0;
-        for (int k = 0; k < r; ++k) {
-            const double pk = P[(size_t)k * rmax + i];
-            a1 += pk * su[k];
-            a2 += pk * sv[k];
+        for (int k0 = 0; k0 < r; k0 += SU) {
+            double pv[SU];
+#pragma unroll
+            for (int e = 0; e < SU; ++e) pv[e] = P[(size_t)(k0 + e < r ? k0 + e : r - 1) * rmax + i];
+#pragma unroll
+            for (int e = 0; e < SU; ++e)
+                if (k0 + e < r) {
+                    a1 += pv[e] * su[k0 + e];
+                    a2 += pv[e] * sv[k0 + e];
+                }
         }
         su2[i] = a1;
         sv2[i] = a2;
     }
     __syncthreads();
     if (fd) {
-        hmul(H, rmax, su2, sh, r);
-        hmul(H, rmax, sv2, sh2, r);
+        hmul_batched(H, rmax, su2, sh, r);
+        hmul_batched(H, rmax, sv2, sh2, r);
         __syncthreads();
         su2 = sh;
         sv2 = sh2;
     }
     for (int j = tid; j < m; j += NT) {
         double a1 = 0.0, a2 = 0.0, a3 = sg[j];
-        for (int k = 0; k < r; ++k) {
-            const double ct = (double)Ct[(size_t)k * ldm + j];
-            a1 += ct * su2[k];
-            a2 += ct * sv2[k];
-            a3 -= (double)C[(size_t)k * ldm + j] * su[k];
+        for (int k0 = 0; k0 < r; k0 += SU) {
+            double ctv[SU], cv[SU];
+#pragma unroll
+            for (int e = 0; e < SU; ++e) {
+                const size_t k = (size_t)(k0 + e < r ? k0 + e : r - 1);
+                ctv[e] = (double)Ct[k * ldm + j];
+                cv[e] = (double)C[k * ldm + j];
+            }
+#pragma unroll
+            for (int e = 0; e < SU; ++e)
+                if (k0 + e < r) {
+                    a1 += ctv[e] * su2[k0 + e];
+                    a2 += ctv[e] * sv2[k0 + e];
+                    a3 -= cv[e] * su[k0 + e];
+                }
         }
         ss[j] = a1;
         st[j] = a2;
