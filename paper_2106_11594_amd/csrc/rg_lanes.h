@@ -3,6 +3,9 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+#include <utility>
+
 namespace rg {
 namespace {
 
@@ -65,6 +68,25 @@ __device__ inline double scatter4(double v0, double v1, double v2, double v3) {
     // rows 0,1 now hold partials of v0 / v1, rows 2,3 of v2 / v3
     const double u0 = swap_add32(v0, v2), u1 = swap_add32(v1, v3);
     return swap_add16(u0, u1);
+}
+
+// Value of v on lane K of this lane's DPP row of 16 (row_newbcast: one
+// 64-bit move, the result in a vector register).
+template <int K>
+__device__ inline double bcast16(double v) {
+    static_assert(K >= 0 && K < 16, "lane within a row of 16");
+    return __builtin_amdgcn_mov_dpp(v, 0x150 + K, 0xF, 0xF, false);
+}
+
+// f(std::integral_constant<int, k>{}) for k = 0 .. N-1 in order, so that k can
+// select an immediate such as a DPP control.
+template <typename F, int... K>
+__device__ inline void static_for_impl(F &&f, std::integer_sequence<int, K...>) {
+    (f(std::integral_constant<int, K>{}), ...);
+}
+template <int N, typename F>
+__device__ inline void static_for(F &&f) {
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
 // Value of v on lane `lane` (wave-uniform lane index), for doubles.

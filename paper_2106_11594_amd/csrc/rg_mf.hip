@@ -952,10 +952,13 @@ __device__ __forceinline__ void push_stream(const PushArgs<typename K::E> &a, in
 
             // ---- Cholesky S = L L^T (lane i holds row i), c = L^-1 (y - G w) ----
             // Wave 0 factors S column by column, lane i holding row i (the four
-            // DPP rows of the wave hold copies).  Column k of the trailing matrix
-            // is broadcast from the lanes that hold it (lane reads, no LDS round
-            // trip), every lane scales and updates its own row.  A pivot that is
-            // not positive and finite ends the prefix of applied rows (ndd); what
+            // DPP rows of the wave hold copies).  Row k of the trailing matrix is
+            // broadcast from lane k of each row of 16 lanes (one 64-bit DPP move
+            // per entry) and stands for column k, S being symmetric: each step is
+            // an elimination step, row i -= (S[i][k] / S[k][k]) row k, which in
+            // exact arithmetic is the outer-product update of the lower triangle;
+            // every lane scales and updates its own row.  A pivot that is not
+            // positive and finite ends the prefix of applied rows (ndd); what
             // follows it is computed but never used.
             // Z to LDS for the substitution (every read of G ended at the barrier
             // above), before the factorization, so that Z need not stay in registers
@@ -979,12 +982,12 @@ __device__ __forceinline__ void push_stream(const PushArgs<typename K::E> &a, in
                 for (int cc = 0; cc < 16; ++cc) srow[cc] = sum_rows(srow[cc]) + ((cc == li && !indblk) ? 1.0 : 0.0);
                 double cy = rowok ? dyi : 0.0;
                 double mypiv = 1.0, myc = 0.0, myinv = 0.0;
+                static_for<16>([&](auto kc) {
+                    constexpr int k = decltype(kc)::value;
+                    double cv[16];  // row k: S[k][j] from lane k of the row of 16, j >= k
 #pragma unroll
-                for (int k = 0; k < 16; ++k) {
-                    double cv[16];  // column k: S[j][k] on lane j, j >= k
-#pragma unroll
-                    for (int j = k; j < 16; ++j) cv[j] = read_lane(srow[k], j);
-                    const double cyk = read_lane(cy, k);
+                    for (int j = k; j < 16; ++j) cv[j] = bcast16<k>(srow[j]);
+                    const double cyk = bcast16<k>(cy);
                     const double piv = cv[k];
                     const double inv = rsqrt_f64(piv), lkk = piv * inv;
                     const double ck = cyk * inv;
@@ -1002,7 +1005,7 @@ __device__ __forceinline__ void push_stream(const PushArgs<typename K::E> &a, in
                     cy -= lik * ck;
 #pragma unroll
                     for (int j = k + 1; j < 16; ++j) srow[j] -= fik * cv[j];
-                }
+                });
                 if (!indblk) {
                 const uint64_t badp = __ballot(!(mypiv > 0.0 && isfinite(mypiv))) & 0xFFFFull;
                 const int nbad = badp ? (int)__builtin_ctzll(badp) : 16;
